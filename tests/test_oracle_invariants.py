@@ -1,0 +1,100 @@
+"""Properties of the race model that hold for any parameters, checked on the
+CPU oracle: complete tallies, label symmetry, resume from an in-play state,
+chunking of the simulation range, winner-only runs, RP(0) estimates."""
+import numpy as np
+import pytest
+from scipy import stats
+
+from paper_2108_02419_amd import inputs
+
+
+def _cfg0():
+    return inputs.start_config(inputs.CFG_START_N5)
+
+
+def test_tallies_complete(orc):
+    c = _cfg0()
+    orders, wins, steps = orc.race_sim(c["comp"], c["L"], 2000, c["seed"])
+    assert wins.sum() == 2000
+    # every sim ranks every competitor exactly once
+    assert (np.sort(orders, axis=1) == np.arange(5, dtype=np.uint8)[None, :]).all()
+    np.testing.assert_array_equal(np.bincount(orders[:, 0], minlength=5), wins)
+    p = orc.win_probs(wins)
+    assert abs(p.sum() - 1.0) <= 1e-15
+    assert steps > 2000 * 5 * 250
+
+
+def test_rp0_estimate_is_uniform(orc):
+    p = orc.win_probs(np.zeros(7, np.uint64))
+    np.testing.assert_array_equal(p, np.full(7, 1 / 7))
+
+
+def test_identical_competitors_give_uniform_winner(orc):
+    comp = np.array([[3.0, 9.0, 1.0, 0.1, 2.0]] * 4, np.float32)
+    N = 200_000
+    _, wins, _ = orc.race_sim(comp, 2000.0, N, seed=8, stop_after=1, want_orders=False, threads=8)
+    chi2 = stats.chisquare(wins.astype(np.float64)).pvalue
+    assert chi2 > 1e-4, wins
+
+
+def test_resume_from_inplay_state_is_bit_identical(orc):
+    c = _cfg0()
+    seed, req = 123, 9
+    sims = [0, 1, 17, 999]
+    for j in sims:
+        full, _, steps_full = orc.race_sim(c["comp"], c["L"], 1, seed, request=req, sim_begin=j)
+        for target in [1.0, 500.0, 1700.0]:
+            t, pos, prev = orc.race_prefix(c["comp"], c["L"], seed, req, j, target)
+            assert t > 0 and pos.max() >= target
+            part, _, steps_rest = orc.race_sim(c["comp"], c["L"], 1, seed, request=req,
+                                               sim_begin=j, state=(t, pos, prev))
+            np.testing.assert_array_equal(part, full)
+            assert steps_rest == steps_full - 5 * t
+
+
+def test_chunking_and_threads_do_not_change_results(orc):
+    c = _cfg0()
+    whole, w, s = orc.race_sim(c["comp"], c["L"], 1000, c["seed"], threads=1)
+    a, wa, sa = orc.race_sim(c["comp"], c["L"], 300, c["seed"], sim_begin=0, threads=4)
+    b, wb, sb = orc.race_sim(c["comp"], c["L"], 700, c["seed"], sim_begin=300, threads=3)
+    np.testing.assert_array_equal(whole, np.concatenate([a, b]))
+    np.testing.assert_array_equal(w, wa + wb)
+    assert s == sa + sb
+
+
+def test_winner_only_run_agrees_with_full_order(orc):
+    c = _cfg0()
+    full, wf, sf = orc.race_sim(c["comp"], c["L"], 1000, c["seed"])
+    win, ww, sw = orc.race_sim(c["comp"], c["L"], 1000, c["seed"], stop_after=1)
+    np.testing.assert_array_equal(full[:, 0], win[:, 0])
+    np.testing.assert_array_equal(wf, ww)
+    assert sw < sf
+    # later ranks are unranked unless they crossed in the winner's tick
+    assert (win[:, 1:] == 0xFF).mean() > 0.9
+
+
+def test_seed_and_request_change_the_stream(orc):
+    c = _cfg0()
+    a, _, _ = orc.race_sim(c["comp"], c["L"], 300, 1)
+    b, _, _ = orc.race_sim(c["comp"], c["L"], 300, 2)
+    d, _, _ = orc.race_sim(c["comp"], c["L"], 300, 1, request=1)
+    assert (a != b).any(axis=1).mean() > 0.5
+    assert (a != d).any(axis=1).mean() > 0.5
+
+
+def test_estimates_converge_like_one_over_sqrt_n(orc):
+    """The RP(d) estimate sharpens as d grows (Section 3): the error of the
+    frequentist estimate against a 400k-sim reference shrinks ~ 1/sqrt(d)."""
+    c = _cfg0()
+    _, wref, _ = orc.race_sim(c["comp"], c["L"], 400_000, 77, stop_after=1, want_orders=False,
+                              threads=8)
+    pref = wref / wref.sum()
+    errs = []
+    for d in [100, 1600]:
+        e = []
+        for k in range(40):
+            _, w, _ = orc.race_sim(c["comp"], c["L"], d, 1000 + k, stop_after=1, want_orders=False)
+            e.append(np.abs(w / d - pref).max())
+        errs.append(np.mean(e))
+    ratio = errs[0] / errs[1]
+    assert 2.5 < ratio < 6.5, errs  # sqrt(16) = 4
