@@ -1,0 +1,153 @@
+"""ctypes binding of ``libbbe.so`` (C ABI in ``include/bbe.h``).
+
+Argument marshalling only: every step of the race model runs in the HIP
+kernels of the library.  PyTorch supplies device memory (CUDA tensors) and
+the stream (``torch.cuda.current_stream()``).  There is no fallback: if the
+library is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbbe.so")
+
+OK, EINVAL, ENOMEM, EDEVICE = 0, -1, -2, -3
+MAX_COMPETITORS = 20
+UNRANKED = 0xFF
+TICK_LIMIT = 1 << 20
+
+
+class BBEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"[{code}] {msg}")
+        self.code = code
+
+
+class Competitor(ctypes.Structure):
+    _fields_ = [("lo", ctypes.c_float), ("hi", ctypes.c_float), ("pref", ctypes.c_float),
+                ("rho", ctypes.c_float), ("theta", ctypes.c_float)]
+
+
+class State(ctypes.Structure):
+    _fields_ = [("tick", ctypes.c_uint32), ("pos", ctypes.c_void_p),
+                ("prev_step", ctypes.c_void_p)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported function declared in include/*.h
+_P, _I, _U32, _U64, _F = ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_float
+SIGNATURES = {
+    "bbe_race_init": (_I, [_P, _I, _F, _P]),
+    "bbe_race_free": (None, [_P]),
+    "bbe_race_n": (_I, [_P]),
+    "bbe_race_sim": (_I, [_P, _P, _U32, _U32, _U64, _U32, _I, _P, _P, _P, _P]),
+    "bbe_win_probs": (_I, [_P, _I, _I, _I, _P, _P]),
+    "bbe_race_prefix": (_I, [_P, _P, _U64, _U32, _U32, _F, _P, _P, _P, _P]),
+    "bbe_last_error": (ctypes.c_char_p, []),
+}
+
+
+def lib() -> ctypes.CDLL:
+    """Load the library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise BBEError(EDEVICE, f"{LIB_PATH} not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise BBEError(rc, lib().bbe_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Race:
+    """A validated race: n competitors (rows lo, hi, pref, rho, theta) on a
+    track of length ``track_len``."""
+
+    def __init__(self, comp, track_len: float):
+        comp = np.ascontiguousarray(comp, dtype=np.float32)
+        if comp.ndim != 2 or comp.shape[1] != 5:
+            raise BBEError(EINVAL, "comp must be [n, 5]")
+        self.n = int(comp.shape[0])
+        self.comp = comp
+        self.track_len = float(track_len)
+        arr = (Competitor * max(self.n, 1))(*[Competitor(*map(float, r)) for r in comp])
+        h = ctypes.c_void_p()
+        _check(lib().bbe_race_init(arr, self.n, self.track_len, ctypes.byref(h)))
+        self._h = h
+
+    @property
+    def handle(self):
+        return self._h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.bbe_race_free(h)
+            self._h = None
+
+
+def _state_struct(state, n):
+    """(tick, pos, prev) host arrays -> (State, keepalive)."""
+    if state is None:
+        return None, None
+    t, pos, prev = state
+    pos = np.ascontiguousarray(pos, dtype=np.float32)
+    prev = np.ascontiguousarray(prev, dtype=np.float32)
+    if pos.shape != (n,) or prev.shape != (n,):
+        raise BBEError(EINVAL, "state arrays must have n entries")
+    st = State(int(t), pos.ctypes.data, prev.ctypes.data)
+    return st, (pos, prev)
+
+
+def race_sim(race: Race, n_sims: int, seed: int, request: int = 0, state=None,
+             sim_begin: int = 0, stop_after: int | None = None, orders=None, wins=None,
+             steps=None, stream=None):
+    """Enqueue ``bbe_race_sim``.  ``orders`` (uint8 [n_sims, n]), ``wins``
+    (int64 [n]) and ``steps`` (int64 [1]) are CUDA tensors or None."""
+    st, keep = _state_struct(state, race.n)
+    stop_after = race.n if stop_after is None else int(stop_after)
+    _check(lib().bbe_race_sim(race.handle, ctypes.byref(st) if st is not None else None,
+                              sim_begin, n_sims, seed, request, stop_after, _dptr(orders),
+                              _dptr(wins), _dptr(steps), _stream(stream)))
+    del keep
+
+
+def win_probs(wins, probs, n: int | None = None, stream=None):
+    """Enqueue ``bbe_win_probs`` over a 1-D or 2-D int64 CUDA tensor."""
+    w2 = wins.reshape(1, -1) if wins.dim() == 1 else wins
+    rows, stride = w2.shape
+    n = stride if n is None else n
+    _check(lib().bbe_win_probs(_dptr(w2), rows, n, stride, _dptr(probs), _stream(stream)))
+
+
+def race_prefix(race: Race, seed: int, request: int, sim: int, target: float, tick_out,
+                pos_out, prev_out, state=None, stream=None):
+    st, keep = _state_struct(state, race.n)
+    _check(lib().bbe_race_prefix(race.handle, ctypes.byref(st) if st is not None else None, seed,
+                                 request, sim, float(target), _dptr(tick_out), _dptr(pos_out),
+                                 _dptr(prev_out), _stream(stream)))
+    del keep

@@ -1,0 +1,48 @@
+"""Tensor-level helpers over the C ABI: allocate the output tensors on the
+current CUDA device and enqueue the library calls on the current stream.
+
+Every computation runs in the library's kernels; these helpers only size
+buffers and marshal arguments.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _bbe
+from ._bbe import Race
+
+
+def mc(race: Race, n_sims: int, seed: int, request: int = 0, state=None, sim_begin: int = 0,
+       stop_after: int | None = None, want_orders: bool = False, want_steps: bool = True,
+       stream=None, device=None):
+    """Monte-Carlo dry-runs of one race.  Returns a dict of CUDA tensors:
+    ``wins`` (int64 [n]), ``steps`` (int64 [1] or None), ``orders`` (uint8
+    [n_sims, n] or None)."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    wins = torch.empty(race.n, dtype=torch.int64, device=dev)
+    steps = torch.empty(1, dtype=torch.int64, device=dev) if want_steps else None
+    orders = (torch.empty((n_sims, race.n), dtype=torch.uint8, device=dev)
+              if want_orders else None)
+    _bbe.race_sim(race, n_sims, seed, request=request, state=state, sim_begin=sim_begin,
+                  stop_after=stop_after, orders=orders, wins=wins, steps=steps, stream=stream)
+    return dict(wins=wins, steps=steps, orders=orders)
+
+
+def win_probs(wins: torch.Tensor, n: int | None = None, stream=None) -> torch.Tensor:
+    probs = torch.empty(wins.shape, dtype=torch.float64, device=wins.device)
+    _bbe.win_probs(wins, probs, n=n, stream=stream)
+    return probs
+
+
+def prefix(race: Race, seed: int, request: int, sim: int, target: float, state=None,
+           stream=None, device=None):
+    """In-play state after advancing one simulation until the leader reaches
+    ``target``.  Returns CUDA tensors (tick uint32-in-int32 [1], pos [n],
+    prev [n])."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    tick = torch.empty(1, dtype=torch.int32, device=dev)
+    pos = torch.empty(race.n, dtype=torch.float32, device=dev)
+    prev = torch.empty(race.n, dtype=torch.float32, device=dev)
+    _bbe.race_prefix(race, seed, request, sim, target, tick, pos, prev, state=state,
+                     stream=stream)
+    return tick, pos, prev

@@ -1,0 +1,87 @@
+"""The C ABI boundary without a GPU: the library loads, exports every
+function include/*.h declares, and rejects invalid arguments before any
+device work (so these run on the CPU)."""
+import ctypes
+import glob
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2108_02419_amd import _bbe
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(bbe_[a-z0-9_]+)\s*\(", text))
+    return names
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(_bbe.LIB_PATH):
+        pytest.skip("libbbe.so not built")
+    return _bbe.lib()
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = _declared()
+    assert "bbe_race_sim" in names and "bbe_race_init" in names
+    for name in names:
+        assert hasattr(L, name), name
+    assert names <= set(_bbe.SIGNATURES), names - set(_bbe.SIGNATURES)
+
+
+GOOD = [[5.0, 8.0, 1.0, 0.1, 2.0]] * 3
+
+
+@pytest.mark.parametrize("comp,track", [
+    (GOOD[:0], 2000.0), ([[5, 8, 1, 0.1, 2]] * 21, 2000.0), ([[0, 8, 1, 0, 2]], 2000.0),
+    ([[5, 4, 1, 0, 2]], 2000.0), ([[5, 8, 0, 0, 2]], 2000.0), ([[5, 8, 1.5, 0, 2]], 2000.0),
+    ([[5, 8, 1, 1.0, 2]], 2000.0), ([[5, 8, 1, 0, -1]], 2000.0), ([[np.nan, 8, 1, 0, 2]], 2000.0),
+    (GOOD, 0.0), (GOOD, np.inf), ([[1e-4, 8, 1, 0, 2]], 2000.0),
+])
+def test_race_init_rejects(L, comp, track):
+    with pytest.raises(_bbe.BBEError) as ei:
+        _bbe.Race(np.array(comp, np.float32).reshape(-1, 5), track)
+    assert ei.value.code == _bbe.EINVAL
+    assert len(str(ei.value)) > 8
+
+
+def test_race_sim_rejects_before_device_work(L):
+    race = _bbe.Race(np.array(GOOD, np.float32), 2000.0)
+    h = race.handle
+    null = ctypes.c_void_p()
+    cases = [
+        dict(n_sims=0), dict(stop_after=0), dict(stop_after=4),
+        dict(sim_begin=2**32 - 5, n_sims=10),
+    ]
+    for kw in cases:
+        a = dict(sim_begin=0, n_sims=10, stop_after=3)
+        a.update(kw)
+        rc = L.bbe_race_sim(h, None, a["sim_begin"], a["n_sims"], 1, 0, a["stop_after"], null,
+                            null, null, null)
+        assert rc == _bbe.EINVAL, kw
+        assert L.bbe_last_error().decode()
+    bad_states = [
+        (3, [0, 10, 2000], [1, 1, 1]), (3, [0, -1, 20], [1, 1, 1]), (3, [0, 1, 20], [1, 0, 1]),
+        (3, [0, 1, np.nan], [1, 1, 1]), (2**32 - 10, [0, 0, 0], [1, 1, 1]),
+    ]
+    for t, p, q in bad_states:
+        st, keep = _bbe._state_struct((t, np.array(p, np.float32), np.array(q, np.float32)), 3)
+        rc = L.bbe_race_sim(h, ctypes.byref(st), 0, 10, 1, 0, 3, null, null, null, null)
+        assert rc == _bbe.EINVAL, (t, p, q)
+    assert L.bbe_race_sim(None, None, 0, 10, 1, 0, 3, null, null, null, null) == _bbe.EINVAL
+    assert L.bbe_win_probs(None, 1, 3, 3, None, None) == _bbe.EINVAL
+    assert L.bbe_race_prefix(h, None, 1, 0, 0, 2000.0, null, null, null, null) == _bbe.EINVAL
+
+
+def test_last_error_cleared_on_success(L):
+    _bbe.Race(np.array(GOOD, np.float32), 2000.0)
+    assert L.bbe_last_error().decode() == ""

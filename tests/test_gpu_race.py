@@ -1,0 +1,159 @@
+"""GPU parity of the race Monte-Carlo: finish orders, win counts and
+competitor-step counts bit-exact against the CPU oracle on the same seeded
+inputs, through the C ABI."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from gpu_util import announce, require_gpu
+from paper_2108_02419_amd import api, inputs
+from paper_2108_02419_amd._bbe import Race
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "race_rules.json")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _gpu_mc(torch, comp, L, n_sims, seed, request=0, state=None, sim_begin=0, stop_after=None,
+            orders=True):
+    race = Race(comp, L)
+    out = api.mc(race, n_sims, seed, request=request, state=state, sim_begin=sim_begin,
+                 stop_after=stop_after, want_orders=orders)
+    torch.cuda.synchronize()
+    o = out["orders"].cpu().numpy() if orders else None
+    return o, out["wins"].cpu().numpy().astype(np.uint64), int(out["steps"].item())
+
+
+def _compare(torch, orc, comp, L, n_sims, seed, request=0, state=None, sim_begin=0,
+             stop_after=None, threads=8):
+    announce(f"n={comp.shape[0]} sims={n_sims} seed={seed} req={request} begin={sim_begin} "
+             f"stop={stop_after} state={'yes' if state is not None else 'start'}")
+    go, gw, gs = _gpu_mc(torch, comp, L, n_sims, seed, request, state, sim_begin, stop_after)
+    oo, ow, os_ = orc.race_sim(comp, L, n_sims, seed, request=request, state=state,
+                               sim_begin=sim_begin, stop_after=stop_after, threads=threads)
+    np.testing.assert_array_equal(go, oo)
+    np.testing.assert_array_equal(gw, ow)
+    assert gs == os_
+
+
+def test_start_n5_1000_sims(torch, orc):
+    c = inputs.start_config(inputs.CFG_START_N5)
+    _compare(torch, orc, c["comp"], c["L"], c["n_sims"], c["seed"], c["request"])
+
+
+def test_start_n20_slice(torch, orc):
+    c = inputs.start_config(inputs.CFG_START_N20)
+    _compare(torch, orc, c["comp"], c["L"], 20_000, c["seed"], c["request"])
+    _compare(torch, orc, c["comp"], c["L"], 3000, c["seed"], c["request"], stop_after=1)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 4, 7, 8, 12, 16, 19, 20])
+def test_every_competitor_count(torch, orc, n):
+    rng = np.random.default_rng(100 + n)
+    comp = inputs.competitor_params(rng, n)
+    comp[:, 4] = rng.uniform(0.0, 4.0, size=n)  # varied thresholds
+    comp[:, 2] = rng.uniform(0.6, 1.0, size=n)  # varied preference coefficients
+    # 1000 sims over a ragged launch (not a multiple of the workgroup size)
+    _compare(torch, orc, comp, 2000.0, 1000 + 37 * n, seed=n, request=n * 11)
+    _compare(torch, orc, comp, 2000.0, 333, seed=n, request=5, stop_after=max(1, n // 2))
+
+
+def test_sim_offsets_and_chunking(torch, orc):
+    c = inputs.start_config(inputs.CFG_START_N5)
+    _compare(torch, orc, c["comp"], c["L"], 777, 9, request=3, sim_begin=123_456)
+    _compare(torch, orc, c["comp"], c["L"], 50, 9, request=3, sim_begin=2**32 - 50)
+    a, wa, sa = _gpu_mc(torch, c["comp"], c["L"], 1000, 4)
+    b1, wb1, sb1 = _gpu_mc(torch, c["comp"], c["L"], 400, 4, sim_begin=0)
+    b2, wb2, sb2 = _gpu_mc(torch, c["comp"], c["L"], 600, 4, sim_begin=400)
+    np.testing.assert_array_equal(a, np.concatenate([b1, b2]))
+    np.testing.assert_array_equal(wa, wb1 + wb2)
+    assert sa == sb1 + sb2
+
+
+def test_inplay_states(torch, orc):
+    reqs = inputs.batch_requests(n_requests=12)
+    for r in reqs:
+        st = orc.race_prefix(r.comp, inputs.TRACK_LEN, 3, r.prefix_request, 0, r.target)
+        _compare(torch, orc, r.comp, inputs.TRACK_LEN, min(r.n_sims, 1500), 3, request=r.index,
+                 state=st)
+
+
+def test_prefix_generator_matches_oracle(torch, orc):
+    reqs = inputs.batch_requests(n_requests=16)
+    for r in reqs:
+        race = Race(r.comp, inputs.TRACK_LEN)
+        t, p, q = api.prefix(race, 3, r.prefix_request, 0, r.target)
+        torch.cuda.synchronize()
+        ot, op, oq = orc.race_prefix(r.comp, inputs.TRACK_LEN, 3, r.prefix_request, 0, r.target)
+        assert int(t.item()) & 0xFFFFFFFF == ot
+        np.testing.assert_array_equal(p.cpu().numpy(), op)
+        np.testing.assert_array_equal(q.cpu().numpy(), oq)
+
+
+def test_golden_rules_on_gpu(torch, orc):
+    cases = json.load(open(GOLDEN))["cases"]
+    for case in cases:
+        comp = np.array(case["comp"], np.float32)
+        race = Race(comp, case["L"])
+        st = case["state"]
+        state = None if st is None else (st["tick"], np.array(st["pos"], np.float32),
+                                         np.array(st["prev"], np.float32))
+        if case["kind"] == "tick":
+            target = np.nextafter(np.float32(max(st["pos"])), np.float32(np.inf))
+            t, p, q = api.prefix(race, 99, 0, 0, target, state=state)
+            torch.cuda.synchronize()
+            assert int(t.item()) == case["expect"]["tick"], case["name"]
+            np.testing.assert_array_equal(p.cpu().numpy(), np.array(case["expect"]["pos"], np.float32))
+            np.testing.assert_array_equal(q.cpu().numpy(), np.array(case["expect"]["prev"], np.float32))
+        else:
+            o, w, s = _gpu_mc(torch, comp, case["L"], 65, 5, state=state)
+            assert (o == np.array(case["expect"]["order"], np.uint8)[None, :]).all(), case["name"]
+            assert s == 65 * case["expect"]["steps_per_sim"]
+
+
+def test_win_probs_kernel(torch, orc):
+    rng = np.random.default_rng(5)
+    w = rng.integers(0, 10**9, size=(37, 20)).astype(np.int64)
+    w[3] = 0
+    wt = torch.tensor(w, device="cuda")
+    for n in [20, 13, 1]:
+        p = api.win_probs(wt, n=n)
+        torch.cuda.synchronize()
+        got = p.cpu().numpy()[:, :n]
+        for r in range(w.shape[0]):
+            np.testing.assert_array_equal(got[r], orc.win_probs(w[r, :n].astype(np.uint64)))
+
+
+def test_full_size_n20_launch(torch, orc):
+    """The 10^6-simulation, 20-competitor workload in the launch configuration
+    the benchmark times: counts-only launch equals the with-orders launch,
+    totals hold, and sampled simulations equal the oracle one by one."""
+    c = inputs.start_config(inputs.CFG_START_N20)
+    announce("full-size n=20 1e6 sims")
+    race = Race(c["comp"], c["L"])
+    counts = api.mc(race, c["n_sims"], c["seed"], request=c["request"])
+    full = api.mc(race, c["n_sims"], c["seed"], request=c["request"], want_orders=True)
+    torch.cuda.synchronize()
+    wins = counts["wins"].cpu().numpy()
+    orders = full["orders"].cpu().numpy()
+    np.testing.assert_array_equal(wins, full["wins"].cpu().numpy())
+    assert int(counts["steps"].item()) == int(full["steps"].item())
+    assert wins.sum() == c["n_sims"]
+    np.testing.assert_array_equal(np.bincount(orders[:, 0], minlength=20), wins)
+    assert (np.sort(orders, axis=1) == np.arange(20, dtype=np.uint8)[None, :]).all()
+    rng = np.random.default_rng(0)
+    sample = np.concatenate([rng.choice(c["n_sims"], 150, replace=False), [0, c["n_sims"] - 1]])
+    for j in sample:
+        oo, _, _ = orc.race_sim(c["comp"], c["L"], 1, c["seed"], request=c["request"],
+                                sim_begin=int(j))
+        np.testing.assert_array_equal(orders[j], oo[0])
+    p = api.win_probs(counts["wins"])
+    torch.cuda.synchronize()
+    assert abs(p.sum().item() - 1.0) <= 1e-15
