@@ -64,6 +64,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--stop-after", type=int, default=None,
                     help="finishers to resolve per simulation (default: all 20)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="before timing, run one plain device-to-device copy of this many MiB "
+                         "(a reference for the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Monte-Carlo "
@@ -100,6 +103,14 @@ def main() -> int:
         if ev is not None:
             ev[1].record(stream)
         _bbe.win_probs(wins, probs, stream=stream)
+
+    if args.copy_probe_mib:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for w in range(W):
         one_step(0, 10_000 + w)
@@ -152,6 +163,8 @@ def main() -> int:
         "competitor_steps_per_step": avg_csteps,
         "kernel_ms": {"median": km[len(km) // 2], "mean": mean, "min": km[0], "cov": cov},
         "wall_s": wall,
+        "device": {"name": torch.cuda.get_device_name(0),
+                   "cus": torch.cuda.get_device_properties(0).multi_processor_count},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
                      "ops_per_competitor_step": ALGO_OPS_PER_COMPETITOR_STEP},

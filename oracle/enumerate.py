@@ -45,17 +45,13 @@ class Race:
 
 def _ahead(race, d, s, running, c):
     """(gap, previous step) of the nearest running competitor strictly ahead of
-    c; equal gaps go to the lowest index; (inf, None) when nobody is ahead."""
-    best_gap, best_s = None, None
-    for i in sorted(running):
-        if i == c or not (d[i] > d[c]):
-            continue
-        g = f32(d[i] - d[c])
-        if best_gap is None or g < best_gap:
-            best_gap, best_s = g, s[i]
-    if best_gap is None:
+    c -- the smallest position greater than d_c, the lowest index among equal
+    positions; (inf, None) when nobody is ahead."""
+    cands = [i for i in running if i != c and d[i] > d[c]]
+    if not cands:
         return f32(np.inf), None
-    return best_gap, best_s
+    i = min(cands, key=lambda i: (d[i], i))
+    return f32(d[i] - d[c]), s[i]
 
 
 def enumerate_race(comp, L, K, stop_after=None, state=None, max_ticks=64):

@@ -31,9 +31,10 @@
  *   R_c(d) = 1 + rho_c*(2 d_c/L - 1) = alpha_c + beta_c*d_c with
  *   alpha_c = fl(1-rho_c), beta_c = fl(2 rho_c / L), evaluated on the
  *   competitor's own start-of-tick position.
- *   The nearest competitor ahead is the running competitor i != c with
- *   d_i > d_c minimising fl(d_i - d_c); among equal gaps the lowest index.
- *   Nobody ahead means an infinite gap.  Blocked iff gap <= theta_c.
+ *   The nearest competitor ahead is the running competitor i != c with the
+ *   smallest position d_i > d_c, the lowest index among equal positions;
+ *   the gap is fl(d_i - d_c).  Nobody ahead means an infinite gap.
+ *   Blocked iff gap <= theta_c.
  *   Competitors that crossed the line in an earlier tick are no longer
  *   running: they take no step and block nobody.
  *   Same-tick finishers are ordered by the crossing fraction
@@ -168,16 +169,15 @@ static void tick_steps(const orc_race *r, const float *d, const float *s, const 
     const int n = r->n;
     for (int c = 0; c < n; ++c) {
         if (!running[c]) continue;
-        /* nearest running competitor strictly ahead; lowest index on equal gaps */
-        float gap = INFINITY;
-        float s_ahead = 0.0f;
+        /* nearest running competitor strictly ahead: the smallest position
+         * greater than d_c, the lowest index among equal positions */
+        int ahead = -1;
         for (int i = 0; i < n; ++i) {
             if (i == c || !running[i]) continue;
-            if (d[i] > d[c]) {
-                float g = d[i] - d[c];
-                if (g < gap) { gap = g; s_ahead = s[i]; }
-            }
+            if (d[i] > d[c] && (ahead < 0 || d[i] < d[ahead])) ahead = i;
         }
+        float gap = ahead >= 0 ? d[ahead] - d[c] : INFINITY;
+        float s_ahead = ahead >= 0 ? s[ahead] : 0.0f;
         float R = r->alpha[c] + r->beta[c] * d[c];
         if (gap > r->theta[c]) {
             float u;
