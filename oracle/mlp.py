@@ -1,0 +1,146 @@
+"""Float64 reference of the surrogate network and of its encoder.
+
+TEST INFRASTRUCTURE ONLY.  Shares no code with the GPU library.
+
+Network: 160 -> 256 -> 256 -> 256 -> 20, ReLU after the three hidden
+layers, softmax over the slots that hold a competitor (the others are
+masked out), soft cross-entropy against Monte-Carlo win frequencies
+(the frequentist estimates of paper Section 3), Adam (Kingma & Ba, 2015).
+
+Parameters are one flat float32 vector packed as
+  W1 [256,160], b1 [256], W2 [256,256], b2 [256], W3 [256,256], b3 [256],
+  W4 [20,256], b4 [20]                                    (177,940 values)
+with W[n, k] the weight from input k to output n.
+
+Rounding points mirrored from the GPU kernels when ``bf16=True``: the
+input features, the weights used in products, the hidden activations after
+ReLU and the gradients fed to products (dz and the back-propagated
+gradients) are rounded to bfloat16 (round to nearest even); everything else
+is carried in float64 here (float32 on the GPU).  With ``bf16=False`` the
+same formulas run in plain float64, which is what the finite-difference
+check differentiates.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+IN, HID, OUT = 160, 256, 20
+SHAPES = [("W1", (HID, IN)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)),
+          ("W3", (HID, HID)), ("b3", (HID,)), ("W4", (OUT, HID)), ("b4", (OUT,))]
+N_PARAMS = sum(int(np.prod(s)) for _, s in SHAPES)
+
+
+def unpack(flat):
+    out, o = {}, 0
+    for name, shp in SHAPES:
+        k = int(np.prod(shp))
+        out[name] = np.asarray(flat[o:o + k], dtype=np.float64).reshape(shp)
+        o += k
+    return out
+
+
+def pack(d):
+    return np.concatenate([np.asarray(d[name], dtype=np.float64).ravel() for name, _ in SHAPES])
+
+
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _r(x, on):
+    return bf16(x) if on else np.asarray(x, dtype=np.float64)
+
+
+def forward(params, X, n_valid, bf16_on=True):
+    """Logits [B, 20] (masked slots -inf), probabilities, and the cache."""
+    P = unpack(params)
+    x = _r(X, bf16_on)
+    W = {k: _r(P[k], bf16_on) if k.startswith("W") else P[k] for k in P}
+    a1 = x @ W["W1"].T + W["b1"]
+    h1 = _r(np.maximum(a1, 0.0), bf16_on)
+    a2 = h1 @ W["W2"].T + W["b2"]
+    h2 = _r(np.maximum(a2, 0.0), bf16_on)
+    a3 = h2 @ W["W3"].T + W["b3"]
+    h3 = _r(np.maximum(a3, 0.0), bf16_on)
+    z = h3 @ W["W4"].T + W["b4"]
+    mask = np.arange(OUT)[None, :] < np.asarray(n_valid)[:, None]
+    zm = np.where(mask, z, -np.inf)
+    zmax = zm.max(axis=1, keepdims=True)
+    e = np.where(mask, np.exp(zm - zmax), 0.0)
+    q = e / e.sum(axis=1, keepdims=True)
+    cache = dict(x=x, W=W, h1=h1, h2=h2, h3=h3, mask=mask)
+    return zm, q, cache
+
+
+def entropy(q):
+    with np.errstate(divide="ignore", invalid="ignore"):
+        t = np.where(q > 0, -q * np.log(q), 0.0)
+    return t.sum(axis=1)
+
+
+def loss_and_grad(params, X, n_valid, target, bf16_on=True):
+    """Mean soft cross-entropy over the batch and its gradient (flat)."""
+    B = X.shape[0]
+    z, q, c = forward(params, X, n_valid, bf16_on)
+    mask = c["mask"]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        logq = np.where(mask, np.log(np.where(mask, q, 1.0)), 0.0)
+    loss = -(np.asarray(target, np.float64) * logq).sum() / B
+    dz = np.where(mask, (q - target) / B, 0.0)
+    W = c["W"]
+    g = {}
+    d4 = _r(dz, bf16_on)
+    g["W4"] = d4.T @ c["h3"]
+    g["b4"] = d4.sum(axis=0)
+    d3 = _r((d4 @ W["W4"]) * (c["h3"] > 0), bf16_on)
+    g["W3"] = d3.T @ c["h2"]
+    g["b3"] = d3.sum(axis=0)
+    d2 = _r((d3 @ W["W3"]) * (c["h2"] > 0), bf16_on)
+    g["W2"] = d2.T @ c["h1"]
+    g["b2"] = d2.sum(axis=0)
+    d1 = _r((d2 @ W["W2"]) * (c["h1"] > 0), bf16_on)
+    g["W1"] = d1.T @ c["x"]
+    g["b1"] = d1.sum(axis=0)
+    return loss, pack(g)
+
+
+def adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba 2015, Algorithm 1) -> (params, m, v)."""
+    m = beta1 * m + (1.0 - beta1) * grad
+    v = beta2 * v + (1.0 - beta2) * grad * grad
+    mhat = m / (1.0 - beta1 ** step)
+    vhat = v / (1.0 - beta2 ** step)
+    return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
+
+
+def encode(comp, n, pos, prev, track_len, dt):
+    """Features [B, 160] (float32, before bfloat16 rounding) and the
+    competitor index in each slot [B, 20] (-1 for padding).
+
+    Slots hold the competitors by position, leader first (equal positions:
+    lower index first), padded to 20.  Per slot 8 features, each one float32
+    operation sequence: d/L, (L-d)/L, s/(7.5 dt), (lo+hi)/(15 dt) (the mean
+    free speed over 7.5), (hi-lo)/(hi+lo), rho/0.2, theta/2, and 1 (0 for
+    padding), with 7.5 dt and 15 dt rounded once to float32."""
+    f = np.float32
+    comp = np.asarray(comp, np.float32)
+    B = comp.shape[0]
+    L = f(track_len)
+    c75 = f(f(7.5) * f(dt))
+    c15 = f(f(15.0) * f(dt))
+    X = np.zeros((B, 20, 8), dtype=np.float32)
+    slot = np.full((B, 20), -1, dtype=np.int32)
+    for b in range(B):
+        k = int(n[b])
+        order = sorted(range(k), key=lambda c: (-float(pos[b][c]), c))
+        for r, c in enumerate(order):
+            lo, hi, _, rho, theta = comp[b, c]
+            d, s = f(pos[b][c]), f(prev[b][c])
+            X[b, r] = [f(d / L), f(f(L - d) / L), f(s / c75), f(f(lo + hi) / c15),
+                       f(f(hi - lo) / f(hi + lo)), f(rho / f(0.2)), f(theta / f(2.0)), f(1.0)]
+            slot[b, r] = c
+    return X.reshape(B, 160), slot

@@ -1,0 +1,116 @@
+"""Pins of the float64 surrogate reference (oracle/mlp.py): central finite
+differences of the loss, closed forms of softmax cross-entropy and of the
+first Adam step, and properties of the state encoding."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+
+
+def _rand_net(rng, scale=0.2):
+    return rng.normal(0, scale, size=mlp.N_PARAMS)
+
+
+def _batch(rng, B):
+    X = rng.normal(0, 1, size=(B, mlp.IN))
+    n = rng.integers(1, 21, size=B)
+    n[0] = 20
+    T = rng.random((B, mlp.OUT)) * (np.arange(mlp.OUT)[None, :] < n[:, None])
+    T /= T.sum(axis=1, keepdims=True)
+    return X, n, T
+
+
+def test_parameter_count():
+    assert mlp.N_PARAMS == 177_940
+
+
+def test_gradient_matches_central_differences():
+    rng = np.random.default_rng(0)
+    p = _rand_net(rng)
+    X, n, T = _batch(rng, 6)
+    loss, g = mlp.loss_and_grad(p, X, n, T, bf16_on=False)
+    idx = np.concatenate([rng.choice(mlp.N_PARAMS, 150, replace=False),
+                          np.arange(mlp.N_PARAMS - 20, mlp.N_PARAMS),   # b4
+                          np.arange(160 * 256, 160 * 256 + 10)])        # b1
+    h = 1e-6
+    for i in idx:
+        e = np.zeros_like(p)
+        e[i] = h
+        lp, _ = mlp.loss_and_grad(p + e, X, n, T, bf16_on=False)
+        lm, _ = mlp.loss_and_grad(p - e, X, n, T, bf16_on=False)
+        fd = (lp - lm) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+
+
+def test_softmax_cross_entropy_closed_forms():
+    rng = np.random.default_rng(1)
+    p = _rand_net(rng)
+    X, n, T = _batch(rng, 5)
+    z, q, _ = mlp.forward(p, X, n, bf16_on=False)
+    # probabilities on the valid slots only, summing to one
+    for b in range(5):
+        assert (q[b, n[b]:] == 0).all()
+        assert abs(q[b, :n[b]].sum() - 1) < 1e-12
+    # shifting b4 (every logit by the same constant) changes nothing
+    P = mlp.unpack(p)
+    P["b4"] = P["b4"] + 3.25
+    _, q2, _ = mlp.forward(mlp.pack(P), X, n, bf16_on=False)
+    np.testing.assert_allclose(q2, q, atol=1e-12)
+    # loss against the network's own output is its entropy (mean)
+    loss, g = mlp.loss_and_grad(p, X, n, q, bf16_on=False)
+    assert abs(loss - mlp.entropy(q).mean()) < 1e-12
+    # ... and its gradient vanishes
+    assert np.abs(g).max() < 1e-12
+
+
+def test_bf16_rounding_is_nearest_even():
+    x = np.array([1.0, 1.0 + 2**-8, 1.0 + 3 * 2**-9, 1.0 + 2**-9, -2.5, 0.0, 3.0e38])
+    r = mlp.bf16(x)
+    assert r[0] == 1.0
+    assert r[1] == 1.0          # halfway, ties to even (mantissa 0)
+    assert r[2] == 1.0 + 2**-7  # 1.5 ulps rounds up
+    assert r[3] == 1.0          # below halfway
+    assert r[4] == -2.5 and r[5] == 0.0
+    assert mlp.bf16(1.0 + 3 * 2**-8) == 1.0 + 2**-6  # halfway, ties to even (mantissa 2)
+
+
+def test_first_adam_step_closed_form():
+    rng = np.random.default_rng(2)
+    w = rng.normal(size=50)
+    g = rng.normal(size=50)
+    lr = 1e-3
+    w1, m, v = mlp.adam(w, g, np.zeros(50), np.zeros(50), 1, lr)
+    # bias-corrected first moments equal g and g^2, so the step is lr*g/(|g|+eps)
+    np.testing.assert_allclose(w1, w - lr * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-15)
+    np.testing.assert_allclose(m, 0.1 * g)
+    np.testing.assert_allclose(v, 0.001 * g * g)
+
+
+def test_encoding_by_hand_and_label_invariance():
+    comp = np.zeros((1, 20, 5), np.float32)
+    comp[0, :3] = [[5, 9, 1, 0.1, 2], [6, 8, 1, -0.2, 1], [4, 10, 1, 0, 3]]
+    pos = np.zeros((1, 20), np.float32)
+    prev = np.zeros((1, 20), np.float32)
+    pos[0, :3] = [1000, 1500, 1000]
+    prev[0, :3] = [0.75, 0.6, 0.5]
+    X, slot = mlp.encode(comp, [3], pos, prev, 2000.0, 0.1)
+    assert slot[0, :4].tolist() == [1, 0, 2, -1]  # leader first, tie by index
+    f = X.reshape(20, 8)
+    np.testing.assert_array_equal(f[0], np.array([0.75, 0.25, np.float32(0.6) / np.float32(0.75),
+                                                  np.float32(14.0) / np.float32(1.5),
+                                                  np.float32(2) / np.float32(14),
+                                                  np.float32(-0.2) / np.float32(0.2), 0.5, 1.0],
+                                                 np.float32))
+    assert (f[3:] == 0).all()
+    # relabelling the competitors permutes nothing in the encoding
+    perm = [2, 0, 1]
+    comp2 = comp.copy()
+    pos2, prev2 = pos.copy(), prev.copy()
+    comp2[0, :3] = comp[0, perm]
+    pos2[0, :3] = pos[0, perm]
+    prev2[0, :3] = prev[0, perm]
+    X2, slot2 = mlp.encode(comp2, [3], pos2, prev2, 2000.0, 0.1)
+    # the tie at 1000 may swap the two tied slots; compare as a multiset of rows
+    a = sorted(map(tuple, X.reshape(20, 8)))
+    b = sorted(map(tuple, X2.reshape(20, 8)))
+    assert a == b
