@@ -140,6 +140,165 @@ int bbe_race_prefix(const bbe_race *race, const bbe_state *state, uint64_t seed,
                     uint32_t request, uint32_t sim, float target, uint32_t *tick_out,
                     float *pos_out, float *prev_out, void *stream);
 
+/* Advances simulation `sim` of stream (seed, request) of `race` from
+ * `state` (NULL = start) by exactly n_ticks ticks (1..BBE_TICK_LIMIT) and
+ * writes the state reached (device outputs as in bbe_race_prefix); used to
+ * step the race that bettors watch in play.  tick_out = 0xFFFFFFFF if a
+ * competitor crosses the line within those ticks.
+ * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
+int bbe_race_advance(const bbe_race *race, const bbe_state *state, uint64_t seed,
+                     uint32_t request, uint32_t sim, uint32_t n_ticks, uint32_t *tick_out,
+                     float *pos_out, float *prev_out, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Batches of uneven requests in one persistent launch.                 */
+/* ------------------------------------------------------------------ */
+
+/* One request of a batch: simulations sim_begin .. sim_begin + n_sims - 1
+ * of stream (seed, request) of `race` from `state` (NULL = start of race),
+ * exactly as one bbe_race_sim call would run them.  stop_after is 1..n, or
+ * 0 for n (the full finish order).  Host pointers; `race` stays owned by
+ * the caller and may be freed once the plan is created.                   */
+typedef struct bbe_request {
+    const bbe_race *race;
+    const bbe_state *state;
+    uint32_t sim_begin;
+    uint32_t n_sims;
+    uint32_t request;
+    int stop_after;
+} bbe_request;
+
+typedef struct bbe_batch_plan bbe_batch_plan;
+
+/* Plan flag: time candidate launch shapes (waves per workgroup, simulations
+ * per work item) on the batch itself and keep the fastest; the choice is
+ * cached per device and batch size class for later plans. */
+#define BBE_PLAN_AUTOTUNE 1u
+
+/* Builds a plan for n_reqs (>= 1) requests (the many dry-run requests of
+ * in-play bettors, paper Section 3 and Section 6): copies the request
+ * descriptors and a work list (requests split into work items of up to 64
+ * simulations per generation, ordered by competitor count and expected
+ * length, longest first) to the device, optionally autotunes, and captures
+ * into a HIP graph the whole launch sequence: clear the outputs, reset the
+ * work queue, run the persistent kernel, compute probabilities.
+ *   win_counts  device uint64[n_reqs][BBE_MAX_COMPETITORS]: row r receives
+ *               request r's win counts (columns >= its n stay 0).
+ *   probs       device double[n_reqs][BBE_MAX_COMPETITORS] or NULL: row r
+ *               receives the win probabilities of request r as
+ *               bbe_win_probs computes them, 0 in the padding columns.
+ *   step_count  device uint64[1] or NULL: total competitor-steps.
+ * The output buffers are bound to the plan and must stay valid while it is
+ * launched.  Runs (and, with BBE_PLAN_AUTOTUNE, times) work on `stream`
+ * and returns after it has completed.
+ * Errors: BBE_EINVAL (any request breaking the rules of bbe_race_sim),
+ * BBE_ENOMEM, BBE_EDEVICE.                                                 */
+int bbe_batch_plan_create(const bbe_request *reqs, int n_reqs, uint64_t seed,
+                          uint64_t *win_counts, double *probs, uint64_t *step_count,
+                          unsigned flags, void *stream, bbe_batch_plan **out);
+
+/* Enqueues one launch of the plan's graph on `stream`.  Launches of one
+ * plan must not overlap (they share the work queue).
+ * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
+int bbe_batch_plan_launch(bbe_batch_plan *plan, void *stream);
+
+/* Launch shape chosen for a plan (any output pointer may be NULL). */
+int bbe_batch_plan_info(const bbe_batch_plan *plan, int *waves_per_block, int *grid,
+                        int *sims_per_item, int *n_items);
+
+/* Releases a plan (NULL is ignored).  Waits for the device to be idle.     */
+void bbe_batch_plan_free(bbe_batch_plan *plan);
+
+/* In-play states for a batch (the batched form of bbe_race_prefix): for
+ * each i < n, advances simulation sims[i] of stream (seed, reqs[i].request)
+ * of reqs[i].race from reqs[i].state until the leader reaches targets[i].
+ * reqs[i].n_sims, sim_begin and stop_after are ignored.  Host inputs;
+ * device outputs tick_out uint32[n] (0xFFFFFFFF if a competitor would
+ * cross first), pos_out and prev_out float[n][BBE_MAX_COMPETITORS]
+ * (competitor order, zero padding).  Returns after the work completed.
+ * Errors: BBE_EINVAL, BBE_ENOMEM, BBE_EDEVICE.                             */
+int bbe_prefix_batch(const bbe_request *reqs, const uint32_t *sims, const float *targets, int n,
+                     uint64_t seed, uint32_t *tick_out, float *pos_out, float *prev_out,
+                     void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Surrogate network: encoded in-play state -> win probabilities.       */
+/* ------------------------------------------------------------------ */
+
+/* A 160 -> 256 -> 256 -> 256 -> 20 perceptron with ReLU hidden layers and a
+ * softmax over the slots that hold a competitor, trained with a soft
+ * cross-entropy against Monte-Carlo win frequencies (the frequentist
+ * estimates of paper Section 3) and Adam (beta1 0.9, beta2 0.999, eps
+ * 1e-8).  Products run on the matrix cores in bfloat16 with float32
+ * accumulation; the master parameters, the Adam moments and the gradients
+ * are float32.
+ *
+ * Parameters travel as one float32 vector of BBE_MLP_NPARAMS values packed
+ * as W1 [256][160], b1 [256], W2 [256][256], b2 [256], W3 [256][256],
+ * b3 [256], W4 [20][256], b4 [20] (W[n][k]: input k to output n).
+ *
+ * Network inputs: x, bfloat16 (uint16 bit patterns) [batch][160] from
+ * bbe_encode_states; n_valid, int32 [batch], the number of slots that hold
+ * a competitor (1..20); slots are in the encoder's order.                  */
+#define BBE_MLP_IN 160
+#define BBE_MLP_HIDDEN 256
+#define BBE_MLP_OUT 20
+#define BBE_MLP_NPARAMS 177940
+
+typedef struct bbe_mlp bbe_mlp;
+
+/* Creates a network from host parameters (copied) with device buffers for
+ * training batches of up to max_batch rows.  Synchronous.
+ * Errors: BBE_EINVAL (non-finite parameter, max_batch < 1), BBE_ENOMEM,
+ * BBE_EDEVICE.                                                              */
+int bbe_mlp_create(const float *params, int max_batch, bbe_mlp **out);
+
+/* Releases a network (NULL is ignored).  Waits for the device.              */
+void bbe_mlp_free(bbe_mlp *m);
+
+/* Copies the float32 master parameters to host memory.  Synchronous.       */
+int bbe_mlp_get_params(const bbe_mlp *m, float *params);
+
+/* Inference on `batch` rows (any size).  Device outputs, each optional:
+ * probs float [batch][20] (0 in empty slots), entropy float [batch]
+ * (natural log), logits float [batch][32] (-inf in empty slots).           */
+int bbe_mlp_forward(const bbe_mlp *m, const uint16_t *x, const int32_t *n_valid, int batch,
+                    float *probs, float *entropy, float *logits, void *stream);
+
+/* Mean soft cross-entropy of `batch` (1..max_batch) rows against target
+ * (device float [batch][20], each row summing to 1 over its valid slots)
+ * into loss (device float[1], overwritten), and its gradient into grad
+ * (device float[BBE_MLP_NPARAMS], overwritten; NULL = the network's own
+ * gradient buffer, used by bbe_mlp_adam_step with grad = NULL).            */
+int bbe_mlp_loss_grad(bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
+                      const float *target, int batch, float *loss, float *grad, void *stream);
+
+/* One Adam step with learning rate lr (> 0) on gradient grad (device, NULL =
+ * the network's own buffer); refreshes the bfloat16 weight copies.         */
+int bbe_mlp_adam_step(bbe_mlp *m, const float *grad, float lr, void *stream);
+
+/* bbe_mlp_loss_grad followed by bbe_mlp_adam_step on the own buffer.       */
+int bbe_mlp_train_step(bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
+                       const float *target, int batch, float lr, float *loss, void *stream);
+
+/* Encodes in-play states for the network.  Device inputs: comp float
+ * [batch][20][5] (lo, hi, pref, rho, theta per competitor), n int32
+ * [batch] (competitors, 1..20), pos and prev float [batch][20] (state, as
+ * in bbe_state).  Slots list the competitors by position, leader first
+ * (equal positions: lower index first), padded to 20; per slot 8 float32
+ * features rounded to bfloat16: d/L, (L-d)/L, s/(7.5 dt), (lo+hi)/(15 dt),
+ * (hi-lo)/(hi+lo), rho/0.2, theta/2, 1 (all 0 for padding), where dt is
+ * the tick length in seconds the race parameters are expressed in.
+ * Outputs: x [batch][160]; slot_comp int32 [batch][20] or NULL, the
+ * competitor in each slot (-1 for padding).  With probs (device double
+ * [batch][20], competitor order, e.g. from bbe_batch_plan_create) the
+ * matching target (device float [batch][20]) receives them in slot order,
+ * 0 for padding: the training labels.  probs and target are both NULL or
+ * both given.                                                                */
+int bbe_encode_states(const float *comp, const int32_t *n, const float *pos, const float *prev,
+                      int batch, float track_len, float dt, uint16_t *x, int32_t *slot_comp,
+                      const double *probs, float *target, void *stream);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *bbe_last_error(void);
 

@@ -37,6 +37,15 @@ class State(ctypes.Structure):
                 ("prev_step", ctypes.c_void_p)]
 
 
+class Request(ctypes.Structure):
+    _fields_ = [("race", ctypes.c_void_p), ("state", ctypes.POINTER(State)),
+                ("sim_begin", ctypes.c_uint32), ("n_sims", ctypes.c_uint32),
+                ("request", ctypes.c_uint32), ("stop_after", ctypes.c_int)]
+
+
+PLAN_AUTOTUNE = 1
+
+
 _lib = None
 
 # (name, restype, argtypes) of every exported function declared in include/*.h
@@ -48,6 +57,20 @@ SIGNATURES = {
     "bbe_race_sim": (_I, [_P, _P, _U32, _U32, _U64, _U32, _I, _P, _P, _P, _P]),
     "bbe_win_probs": (_I, [_P, _I, _I, _I, _P, _P]),
     "bbe_race_prefix": (_I, [_P, _P, _U64, _U32, _U32, _F, _P, _P, _P, _P]),
+    "bbe_batch_plan_create": (_I, [_P, _I, _U64, _P, _P, _P, ctypes.c_uint, _P, _P]),
+    "bbe_batch_plan_launch": (_I, [_P, _P]),
+    "bbe_batch_plan_info": (_I, [_P, _P, _P, _P, _P]),
+    "bbe_batch_plan_free": (None, [_P]),
+    "bbe_prefix_batch": (_I, [_P, _P, _P, _I, _U64, _P, _P, _P, _P]),
+    "bbe_mlp_create": (_I, [_P, _I, _P]),
+    "bbe_mlp_free": (None, [_P]),
+    "bbe_mlp_get_params": (_I, [_P, _P]),
+    "bbe_mlp_forward": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
+    "bbe_mlp_loss_grad": (_I, [_P, _P, _P, _P, _I, _P, _P, _P]),
+    "bbe_mlp_adam_step": (_I, [_P, _P, _F, _P]),
+    "bbe_mlp_train_step": (_I, [_P, _P, _P, _P, _I, _F, _P, _P]),
+    "bbe_encode_states": (_I, [_P, _P, _P, _P, _I, _F, _F, _P, _P, _P, _P, _P]),
+    "bbe_race_advance": (_I, [_P, _P, _U64, _U32, _U32, _U32, _P, _P, _P, _P]),
     "bbe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -150,4 +173,132 @@ def race_prefix(race: Race, seed: int, request: int, sim: int, target: float, ti
     _check(lib().bbe_race_prefix(race.handle, ctypes.byref(st) if st is not None else None, seed,
                                  request, sim, float(target), _dptr(tick_out), _dptr(pos_out),
                                  _dptr(prev_out), _stream(stream)))
+    del keep
+
+
+def _request_array(specs):
+    """specs: sequence of (race, state or None, sim_begin, n_sims, request,
+    stop_after) -> (ctypes array, keepalive)."""
+    keep = []
+    arr = (Request * len(specs))()
+    for i, (race, state, sim_begin, n_sims, request, stop_after) in enumerate(specs):
+        st, k = _state_struct(state, race.n)
+        keep.append((st, k, race))
+        arr[i].race = race.handle
+        arr[i].state = ctypes.pointer(st) if st is not None else None
+        arr[i].sim_begin = int(sim_begin)
+        arr[i].n_sims = int(n_sims)
+        arr[i].request = int(request) & 0xFFFFFFFF
+        arr[i].stop_after = int(stop_after or 0)
+    return arr, keep
+
+
+class BatchPlan:
+    """A plan over uneven requests (``bbe_batch_plan_*``).  Outputs are CUDA
+    tensors bound at creation: ``wins`` int64 [n_reqs, 20], optional
+    ``probs`` float64 [n_reqs, 20] and ``steps`` int64 [1]."""
+
+    def __init__(self, specs, seed: int, wins, probs=None, steps=None, autotune=True,
+                 stream=None):
+        arr, keep = _request_array(specs)
+        h = ctypes.c_void_p()
+        self._outs = (wins, probs, steps)
+        _check(lib().bbe_batch_plan_create(arr, len(specs), seed, _dptr(wins), _dptr(probs),
+                                           _dptr(steps), PLAN_AUTOTUNE if autotune else 0,
+                                           _stream(stream), ctypes.byref(h)))
+        del keep
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(lib().bbe_batch_plan_launch(self._h, _stream(stream)))
+
+    def info(self):
+        v = [ctypes.c_int() for _ in range(4)]
+        _check(lib().bbe_batch_plan_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(waves_per_block=v[0].value, grid=v[1].value, sims_per_item=v[2].value,
+                    n_items=v[3].value)
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.bbe_batch_plan_free(h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+def prefix_batch(specs, sims, targets, seed, tick_out, pos_out, prev_out, stream=None):
+    """Batched in-play states: specs as for BatchPlan (n_sims etc. ignored)."""
+    arr, keep = _request_array(specs)
+    sims = np.ascontiguousarray(sims, dtype=np.uint32)
+    targets = np.ascontiguousarray(targets, dtype=np.float32)
+    _check(lib().bbe_prefix_batch(arr, sims.ctypes.data, targets.ctypes.data, len(specs), seed,
+                                  _dptr(tick_out), _dptr(pos_out), _dptr(prev_out),
+                                  _stream(stream)))
+    del keep
+
+
+MLP_NPARAMS = 177_940
+
+
+class Mlp:
+    """The surrogate network (``bbe_mlp_*``).  Tensors are CUDA tensors:
+    x int16/uint16-bits [B, 160], n_valid int32 [B], target float32 [B, 20]."""
+
+    def __init__(self, params, max_batch: int):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if p.shape != (MLP_NPARAMS,):
+            raise BBEError(EINVAL, f"params must have {MLP_NPARAMS} values")
+        h = ctypes.c_void_p()
+        _check(lib().bbe_mlp_create(p.ctypes.data, int(max_batch), ctypes.byref(h)))
+        self._h = h
+        self.max_batch = int(max_batch)
+
+    def params(self) -> np.ndarray:
+        out = np.empty(MLP_NPARAMS, dtype=np.float32)
+        _check(lib().bbe_mlp_get_params(self._h, out.ctypes.data))
+        return out
+
+    def forward(self, x, n_valid, probs=None, entropy=None, logits=None, stream=None):
+        _check(lib().bbe_mlp_forward(self._h, _dptr(x), _dptr(n_valid), int(x.shape[0]),
+                                     _dptr(probs), _dptr(entropy), _dptr(logits),
+                                     _stream(stream)))
+
+    def loss_grad(self, x, n_valid, target, loss, grad=None, stream=None):
+        _check(lib().bbe_mlp_loss_grad(self._h, _dptr(x), _dptr(n_valid), _dptr(target),
+                                       int(x.shape[0]), _dptr(loss), _dptr(grad),
+                                       _stream(stream)))
+
+    def adam_step(self, lr: float, grad=None, stream=None):
+        _check(lib().bbe_mlp_adam_step(self._h, _dptr(grad), float(lr), _stream(stream)))
+
+    def train_step(self, x, n_valid, target, lr: float, loss, stream=None):
+        _check(lib().bbe_mlp_train_step(self._h, _dptr(x), _dptr(n_valid), _dptr(target),
+                                        int(x.shape[0]), float(lr), _dptr(loss), _stream(stream)))
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.bbe_mlp_free(h)
+        self._h = None
+
+    def __del__(self):
+        self.free()
+
+
+def encode_states(comp, n, pos, prev, track_len: float, dt: float, x, slot=None, probs=None,
+                  target=None, stream=None):
+    """Enqueue ``bbe_encode_states`` on CUDA tensors."""
+    _check(lib().bbe_encode_states(_dptr(comp), _dptr(n), _dptr(pos), _dptr(prev),
+                                   int(n.shape[0]), float(track_len), float(dt), _dptr(x),
+                                   _dptr(slot), _dptr(probs), _dptr(target), _stream(stream)))
+
+
+def race_advance(race: Race, seed: int, request: int, sim: int, n_ticks: int, tick_out,
+                 pos_out, prev_out, state=None, stream=None):
+    st, keep = _state_struct(state, race.n)
+    _check(lib().bbe_race_advance(race.handle, ctypes.byref(st) if st is not None else None,
+                                  seed, request, sim, int(n_ticks), _dptr(tick_out),
+                                  _dptr(pos_out), _dptr(prev_out), _stream(stream)))
     del keep

@@ -1,0 +1,352 @@
+// bbe_batch.hip -- batches of uneven Monte-Carlo requests: request
+// descriptors and the work list on the device, launch-shape autotuning and
+// a captured HIP graph of the whole launch sequence (include/bbe.h).
+#include "abi_internal.hpp"
+
+#include <algorithm>
+#include <map>
+#include <mutex>
+#include <new>
+#include <vector>
+
+using namespace bbe_abi;
+
+namespace {
+
+struct Shape {
+    int waves_per_block;
+    int sims_per_item;  // multiple of 64: one work item = sims_per_item / 64 generations
+};
+
+// Autotune results per (device, size class of the work list).
+std::mutex g_tune_mu;
+std::map<std::pair<int, int>, Shape> g_tuned;
+
+struct Work {
+    std::vector<bbe::Chunk> chunks;
+};
+
+// Expected ticks until the request's simulations end (used only to order
+// the work list): remaining distance over a typical free step.
+double expected_ticks(const bbe::ReqDesc& r) {
+    const int n = r.rc.n;
+    double lead = 0.0, last = 1e30, fast = 0.0, slow = 1e30;
+    for (int k = 0; k < n; ++k) {
+        lead = std::max(lead, (double)r.d0[k]);
+        last = std::min(last, (double)r.d0[k]);
+    }
+    for (int c = 0; c < n; ++c) {
+        double m = (double)r.rc.elo[c] + 0.5 * (double)r.rc.espan[c];
+        fast = std::max(fast, m);
+        slow = std::min(slow, m);
+    }
+    double first = ((double)r.rc.L - lead) / std::max(fast, 1e-30);
+    double all = ((double)r.rc.L - last) / std::max(slow, 1e-30);
+    double f = n > 1 ? (double)(r.stop_after - 1) / (double)(n - 1) : 0.0;
+    return first + f * (all - first);
+}
+
+Work build_work(const std::vector<bbe::ReqDesc>& reqs, int sims_per_item) {
+    Work w;
+    std::vector<std::pair<double, bbe::Chunk>> items;
+    for (size_t r = 0; r < reqs.size(); ++r) {
+        const double est = expected_ticks(reqs[r]);
+        for (uint32_t first = 0; first < reqs[r].n_sims; first += sims_per_item) {
+            bbe::Chunk c;
+            c.req = (uint32_t)r;
+            c.first = first;
+            c.count = std::min<uint32_t>(sims_per_item, reqs[r].n_sims - first);
+            c.n = (uint32_t)reqs[r].rc.n;
+            items.push_back({est, c});
+        }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) {
+        if (a.second.n != b.second.n) return a.second.n > b.second.n;
+        return a.first > b.first;
+    });
+    w.chunks.reserve(items.size());
+    for (auto& it : items) w.chunks.push_back(it.second);
+    return w;
+}
+
+int size_class(size_t n_chunks) {
+    int c = 0;
+    while (n_chunks > 1) {
+        n_chunks >>= 1;
+        ++c;
+    }
+    return c;
+}
+
+}  // namespace
+
+struct bbe_batch_plan {
+    int device = 0;
+    int n_reqs = 0;
+    bbe::ReqDesc* d_reqs = nullptr;
+    bbe::Chunk* d_chunks = nullptr;
+    size_t chunk_cap = 0;
+    uint32_t* d_queue = nullptr;
+    uint32_t n_chunks = 0;
+    uint32_t k0 = 0, k1 = 0;
+    unsigned long long* wins = nullptr;
+    double* probs = nullptr;
+    unsigned long long* steps = nullptr;
+    Shape shape{4, 64};
+    int grid = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::vector<bbe::ReqDesc> host_reqs;
+};
+
+namespace {
+
+hipError_t enqueue(bbe_batch_plan* p, hipStream_t s) {
+    hipError_t e;
+    if ((e = bbe::launch_zero_u64(p->wins, p->n_reqs * bbe::kMaxN, s)) != hipSuccess) return e;
+    if (p->steps && (e = bbe::launch_zero_u64(p->steps, 1, s)) != hipSuccess) return e;
+    if ((e = bbe::launch_fill_u32(p->d_queue, 0u, 1, s)) != hipSuccess) return e;
+    bbe::BatchArgs a;
+    a.reqs = p->d_reqs;
+    a.chunks = p->d_chunks;
+    a.n_chunks = p->n_chunks;
+    a.queue = p->d_queue;
+    a.wins = p->wins;
+    a.steps = p->steps;
+    a.k0 = p->k0;
+    a.k1 = p->k1;
+    if ((e = bbe::launch_batch_mc(a, p->shape.waves_per_block, p->grid, s)) != hipSuccess) return e;
+    if (p->probs &&
+        (e = bbe::launch_batch_probs(p->wins, p->d_reqs, p->n_reqs, p->probs, s)) != hipSuccess)
+        return e;
+    return hipSuccess;
+}
+
+int upload_work(bbe_batch_plan* p, const Shape& sh) {
+    Work w = build_work(p->host_reqs, sh.sims_per_item);
+    if (w.chunks.size() > p->chunk_cap) {
+        if (p->d_chunks) (void)hipFree(p->d_chunks);
+        p->d_chunks = nullptr;
+        p->chunk_cap = 0;
+        if (hipMalloc(&p->d_chunks, w.chunks.size() * sizeof(bbe::Chunk)) != hipSuccess)
+            return fail(BBE_ENOMEM, "device allocation of the work list failed");
+        p->chunk_cap = w.chunks.size();
+    }
+    hipError_t e = hipMemcpy(p->d_chunks, w.chunks.data(), w.chunks.size() * sizeof(bbe::Chunk),
+                             hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "copying the work list");
+    p->n_chunks = (uint32_t)w.chunks.size();
+    p->shape = sh;
+    p->grid = bbe::batch_blocks_per_cu(sh.waves_per_block) * device_cus();
+    return BBE_OK;
+}
+
+void destroy(bbe_batch_plan* p) {
+    if (!p) return;
+    if (p->d_reqs || p->d_chunks || p->d_queue || p->exec) (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->d_reqs) (void)hipFree(p->d_reqs);
+    if (p->d_chunks) (void)hipFree(p->d_chunks);
+    if (p->d_queue) (void)hipFree(p->d_queue);
+    delete p;
+}
+
+int fill_desc(const bbe_request& q, int idx, bbe::ReqDesc& d) {
+    if (!q.race) return fail(BBE_EINVAL, "request %d: race is NULL", idx);
+    std::memset(&d, 0, sizeof d);
+    d.rc = q.race->rc;
+    int rc = check_state(q.race, q.state, d.d0, d.s0, d.id0, &d.t0);
+    if (rc != BBE_OK) return fail(rc, "request %d: %s", idx, g_err.c_str());
+    d.request = q.request;
+    d.sim_begin = q.sim_begin;
+    d.n_sims = q.n_sims;
+    d.stop_after = q.stop_after == 0 ? q.race->n : q.stop_after;
+    return BBE_OK;
+}
+
+}  // namespace
+
+BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t seed,
+                                  uint64_t* win_counts, double* probs, uint64_t* step_count,
+                                  unsigned flags, void* stream, bbe_batch_plan** out) {
+    if (!out) return fail(BBE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!reqs || n_reqs < 1) return fail(BBE_EINVAL, "need n_reqs >= 1 requests");
+    if (!win_counts) return fail(BBE_EINVAL, "win_counts is NULL");
+    bbe_batch_plan* p = new (std::nothrow) bbe_batch_plan();
+    if (!p) return fail(BBE_ENOMEM, "out of host memory");
+    p->n_reqs = n_reqs;
+    p->host_reqs.resize(n_reqs);
+    for (int i = 0; i < n_reqs; ++i) {
+        const bbe_request& q = reqs[i];
+        int rc = fill_desc(q, i, p->host_reqs[i]);
+        if (rc != BBE_OK) {
+            destroy(p);
+            return rc;
+        }
+        if (q.n_sims == 0) {
+            destroy(p);
+            return fail(BBE_EINVAL, "request %d: n_sims must be >= 1", i);
+        }
+        if ((uint64_t)q.sim_begin + q.n_sims > 0x100000000ull) {
+            destroy(p);
+            return fail(BBE_EINVAL, "request %d: sim_begin + n_sims exceeds 2^32", i);
+        }
+        if (q.stop_after < 0 || q.stop_after > q.race->n) {
+            destroy(p);
+            return fail(BBE_EINVAL, "request %d: stop_after = %d outside 0..%d", i,
+                        q.stop_after, q.race->n);
+        }
+    }
+    p->k0 = (uint32_t)seed;
+    p->k1 = (uint32_t)(seed >> 32);
+    p->wins = reinterpret_cast<unsigned long long*>(win_counts);
+    p->probs = probs;
+    p->steps = reinterpret_cast<unsigned long long*>(step_count);
+    (void)hipGetDevice(&p->device);
+
+    hipError_t e;
+    if (hipMalloc(&p->d_reqs, sizeof(bbe::ReqDesc) * n_reqs) != hipSuccess ||
+        hipMalloc(&p->d_queue, sizeof(uint32_t)) != hipSuccess) {
+        destroy(p);
+        return fail(BBE_ENOMEM, "device allocation of the request table failed");
+    }
+    if ((e = hipMemcpy(p->d_reqs, p->host_reqs.data(), sizeof(bbe::ReqDesc) * n_reqs,
+                       hipMemcpyHostToDevice)) != hipSuccess) {
+        destroy(p);
+        return hip_fail(e, "copying the request table");
+    }
+    if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+        destroy(p);
+        return hip_fail(e, "creating the capture stream");
+    }
+    hipStream_t s = static_cast<hipStream_t>(stream);
+
+    // Launch shape: tuned on this batch, or from the cache, or the default.
+    Shape best{4, 64};
+    size_t base_items = build_work(p->host_reqs, 64).chunks.size();
+    std::pair<int, int> key{p->device, size_class(base_items)};
+    bool have = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tuned.find(key);
+        if (it != g_tuned.end()) {
+            best = it->second;
+            have = true;
+        }
+    }
+    if ((flags & BBE_PLAN_AUTOTUNE) && !have) {
+        const Shape cands[] = {{4, 64}, {2, 64}, {1, 64}, {4, 128}, {2, 128}, {4, 256}};
+        float best_ms = 1e30f;
+        hipEvent_t ev0, ev1;
+        (void)hipEventCreate(&ev0);
+        (void)hipEventCreate(&ev1);
+        for (const Shape& c : cands) {
+            int rc = upload_work(p, c);
+            if (rc != BBE_OK) {
+                (void)hipEventDestroy(ev0);
+                (void)hipEventDestroy(ev1);
+                destroy(p);
+                return rc;
+            }
+            float ms_sum = 0.0f;
+            bool okc = true;
+            for (int rep = 0; rep < 3 && okc; ++rep) {
+                (void)hipEventRecord(ev0, s);
+                okc = enqueue(p, s) == hipSuccess;
+                (void)hipEventRecord(ev1, s);
+                (void)hipEventSynchronize(ev1);
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, ev0, ev1);
+                if (rep > 0) ms_sum += ms;  // first run warms up
+            }
+            if (okc && ms_sum < best_ms) {
+                best_ms = ms_sum;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(ev0);
+        (void)hipEventDestroy(ev1);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[key] = best;
+    }
+    int rc = upload_work(p, best);
+    if (rc != BBE_OK) {
+        destroy(p);
+        return rc;
+    }
+
+    // Capture clear -> queue reset -> persistent kernel -> probabilities.
+    if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) !=
+        hipSuccess) {
+        destroy(p);
+        return hip_fail(e, "beginning graph capture");
+    }
+    hipError_t ee = enqueue(p, p->cap_stream);
+    e = hipStreamEndCapture(p->cap_stream, &p->graph);
+    if (ee != hipSuccess || e != hipSuccess) {
+        destroy(p);
+        return hip_fail(ee != hipSuccess ? ee : e, "capturing the launch sequence");
+    }
+    if ((e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0)) != hipSuccess) {
+        destroy(p);
+        return hip_fail(e, "instantiating the graph");
+    }
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) {
+        destroy(p);
+        return hip_fail(e, "synchronizing after plan set-up");
+    }
+    *out = p;
+    return ok();
+}
+
+BBE_API int bbe_batch_plan_launch(bbe_batch_plan* plan, void* stream) {
+    if (!plan || !plan->exec) return fail(BBE_EINVAL, "plan is NULL");
+    hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching the plan graph");
+    return ok();
+}
+
+BBE_API int bbe_batch_plan_info(const bbe_batch_plan* plan, int* waves_per_block, int* grid,
+                                int* sims_per_item, int* n_items) {
+    if (!plan) return fail(BBE_EINVAL, "plan is NULL");
+    if (waves_per_block) *waves_per_block = plan->shape.waves_per_block;
+    if (grid) *grid = plan->grid;
+    if (sims_per_item) *sims_per_item = plan->shape.sims_per_item;
+    if (n_items) *n_items = (int)plan->n_chunks;
+    return ok();
+}
+
+BBE_API void bbe_batch_plan_free(bbe_batch_plan* plan) { destroy(plan); }
+
+BBE_API int bbe_prefix_batch(const bbe_request* reqs, const uint32_t* sims, const float* targets,
+                             int n, uint64_t seed, uint32_t* tick_out, float* pos_out,
+                             float* prev_out, void* stream) {
+    if (!reqs || !sims || !targets || n < 1) return fail(BBE_EINVAL, "bad batch arguments");
+    if (!tick_out || !pos_out || !prev_out) return fail(BBE_EINVAL, "NULL output");
+    std::vector<bbe::ReqDesc> h(n);
+    for (int i = 0; i < n; ++i) {
+        int rc = fill_desc(reqs[i], i, h[i]);
+        if (rc != BBE_OK) return rc;
+        if (!std::isfinite(targets[i]) || !(targets[i] < reqs[i].race->L))
+            return fail(BBE_EINVAL, "request %d: target must be finite and < track length", i);
+        h[i].prefix_sim = sims[i];
+        h[i].target = targets[i];
+    }
+    bbe::ReqDesc* d = nullptr;
+    if (hipMalloc(&d, sizeof(bbe::ReqDesc) * n) != hipSuccess)
+        return fail(BBE_ENOMEM, "device allocation failed");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(bbe::ReqDesc) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess)
+        e = bbe::launch_prefix_batch(d, n, (uint32_t)seed, (uint32_t)(seed >> 32), tick_out,
+                                     pos_out, prev_out, s);
+    hipError_t e2 = hipStreamSynchronize(s);
+    (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "in-play state batch");
+    if (e2 != hipSuccess) return hip_fail(e2, "in-play state batch");
+    return ok();
+}

@@ -1,0 +1,404 @@
+// mlp_kernels.hip -- the surrogate network on gfx950 matrix cores: a
+// 160 -> 256 -> 256 -> 256 -> 20 perceptron (ReLU, masked softmax) mapping an
+// encoded in-play race state to win probabilities, trained on Monte-Carlo
+// win frequencies (the frequentist estimates of paper Section 3) with a
+// soft cross-entropy and Adam.
+//
+// Products use v_mfma_f32_16x16x32_bf16: bfloat16 operands, float32
+// accumulation.  Operand fragments (one 16x32 block of A, one 32x16 block of
+// B per instruction): lane l holds row / column (l % 16) and the 8
+// consecutive reduction indices 8*(l/16) .. 8*(l/16)+7; the 16x16 float
+// result: lane l holds column (l % 16) of rows 4*(l/16) .. 4*(l/16)+3.
+//
+// Rounding points (round to nearest even): features, weights used in
+// products, hidden activations after ReLU, dz and the back-propagated
+// gradients; biases, logits, probabilities, loss and weight gradients are
+// float32.
+#include "mlp.hpp"
+
+namespace bbe {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(4))) float floatx4;
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+    uint32_t u = __float_as_uint(x);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ floatx4 mfma(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// 16 rows x 32 reduction indices from a row-major LDS tile (stride S).
+__device__ __forceinline__ bf16x8 frag_lds(const uint16_t* t, int S, int row0, int k0, int lane) {
+    return *reinterpret_cast<const bf16x8*>(t + (row0 + (lane & 15)) * S + k0 + 8 * (lane >> 4));
+}
+// 16 rows (of a [N][K] row-major global matrix) x 32 reduction indices.
+__device__ __forceinline__ bf16x8 frag_glb(const uint16_t* __restrict__ W, int K, int n0, int k0,
+                                          int lane) {
+    return *reinterpret_cast<const bf16x8*>(W + (size_t)(n0 + (lane & 15)) * K + k0 +
+                                            8 * (lane >> 4));
+}
+
+// acc[rb][cb] = in[64 x K] (LDS) * W[n_base .. n_base + 16*NCB, 0 .. K)^T
+template <int K, int NCB>
+__device__ __forceinline__ void tile_gemm(const uint16_t* in, int S, const uint16_t* __restrict__ W,
+                                          int n_base, floatx4 (&acc)[4][NCB], int lane) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 a[4], b[NCB];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) a[rb] = frag_lds(in, S, rb * 16, k0, lane);
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) b[cb] = frag_glb(W, K, n_base + cb * 16, k0, lane);
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
+    }
+}
+
+constexpr int kTile = 64;            // rows per workgroup
+constexpr int kS = kHid + 8;         // LDS row stride of hidden tiles (bank spread)
+constexpr int kSin = kIn + 8;        // LDS row stride of the feature tile
+constexpr int kSout = kOutP + 8;     // LDS row stride of the dz tile
+
+// Copies rows [row0, row0 + 64) of a [B][K] bf16 matrix into an LDS tile
+// (stride S), zero rows past B.  16-byte pieces.
+template <int K>
+__device__ __forceinline__ void load_tile(uint16_t* t, int S, const uint16_t* __restrict__ g,
+                                          int row0, int B) {
+    constexpr int P = K / 8;
+    for (int i = threadIdx.x; i < kTile * P; i += blockDim.x) {
+        int r = i / P, c = (i - r * P) * 8;
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if (row0 + r < B) v = *reinterpret_cast<const uint4*>(g + (size_t)(row0 + r) * K + c);
+        *reinterpret_cast<uint4*>(t + r * S + c) = v;
+    }
+}
+
+// Hidden layer epilogue: bias, ReLU, bfloat16 into LDS (and global).
+template <int NCB>
+__device__ __forceinline__ void hidden_out(const floatx4 (&acc)[4][NCB], int n_base,
+                                           const float* __restrict__ bias, uint16_t* out, int S,
+                                           uint16_t* __restrict__ g, int row0, int B, int lane) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < NCB; ++cb) {
+            const int n = n_base + cb * 16 + (lane & 15);
+            const float bn = bias[n];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = rb * 16 + 4 * (lane >> 4) + i;
+                uint16_t h = to_bf16(fmaxf(acc[rb][cb][i] + bn, 0.0f));
+                out[r * S + n] = h;
+                if (g && row0 + r < B) g[(size_t)(row0 + r) * kHid + n] = h;
+            }
+        }
+}
+
+// Forward pass of 64 rows; optional softmax cross-entropy epilogue.
+__global__ void __launch_bounds__(256) mlp_fwd_kernel(const MlpFwdArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t bufA[kTile * kS];
+    __shared__ __attribute__((aligned(16))) uint16_t bufB[kTile * kS];
+    __shared__ float logit[kTile][kOutP + 1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * kTile;
+
+    load_tile<kIn>(bufA, kSin, a.x, row0, a.B);
+    __syncthreads();
+    {
+        floatx4 acc[4][4];
+        tile_gemm<kIn, 4>(bufA, kSin, a.w1, wave * 64, acc, lane);
+        hidden_out<4>(acc, wave * 64, a.b1, bufB, kS, a.h1, row0, a.B, lane);
+    }
+    __syncthreads();
+    {
+        floatx4 acc[4][4];
+        tile_gemm<kHid, 4>(bufB, kS, a.w2, wave * 64, acc, lane);
+        hidden_out<4>(acc, wave * 64, a.b2, bufA, kS, a.h2, row0, a.B, lane);
+    }
+    __syncthreads();
+    {
+        floatx4 acc[4][4];
+        tile_gemm<kHid, 4>(bufA, kS, a.w3, wave * 64, acc, lane);
+        hidden_out<4>(acc, wave * 64, a.b3, bufB, kS, a.h3, row0, a.B, lane);
+    }
+    __syncthreads();
+    if (wave < 2) {  // 32 padded outputs: two column blocks, one per wave
+        floatx4 acc[4][1];
+        tile_gemm<kHid, 1>(bufB, kS, a.w4, wave * 16, acc, lane);
+        const int n = wave * 16 + (lane & 15);
+        const float bn = n < kOut ? a.b4[n] : 0.0f;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) logit[rb * 16 + 4 * (lane >> 4) + i][n] = acc[rb][0][i] + bn;
+    }
+    __syncthreads();
+
+    // Masked softmax over the slots that hold a competitor, one row a thread.
+    const int r = threadIdx.x;
+    if (r < kTile && row0 + r < a.B) {
+        const size_t row = (size_t)(row0 + r);
+        const int nv = min(max(a.n_valid[row], 1), kOut);  // 1..20 slots hold competitors
+        float mx = -__builtin_inff();
+        for (int c = 0; c < nv; ++c) mx = fmaxf(mx, logit[r][c]);
+        float e[kOut], sum = 0.0f;
+        for (int c = 0; c < kOut; ++c) {
+            e[c] = c < nv ? expf(logit[r][c] - mx) : 0.0f;
+            sum += e[c];
+        }
+        const float inv = 1.0f / sum;
+        float ent = 0.0f, ce = 0.0f;
+        for (int c = 0; c < kOut; ++c) {
+            float q = e[c] * inv;
+            if (a.probs) a.probs[row * kOut + c] = q;
+            if (a.logits) a.logits[row * kOutP + c] = c < nv ? logit[r][c] : -__builtin_inff();
+            if (c < nv) {
+                float lq = (logit[r][c] - mx) - logf(sum);
+                if (q > 0.0f) ent -= q * lq;
+                if (a.target) {
+                    float p = a.target[row * kOut + c];
+                    ce -= p * lq;
+                    a.dz[row * kOutP + c] = to_bf16((q - p) * a.inv_batch);
+                }
+            } else if (a.target) {
+                a.dz[row * kOutP + c] = 0;
+            }
+        }
+        if (a.target)
+            for (int c = kOut; c < kOutP; ++c) a.dz[row * kOutP + c] = 0;
+        if (a.entropy) a.entropy[row] = ent;
+        if (a.loss) atomicAdd(a.loss, ce * a.inv_batch);
+    }
+}
+
+// Backward-data epilogue: gradient times ReLU mask of the forward
+// activation, bfloat16 into LDS (if given) and global.
+__device__ __forceinline__ void grad_out(const floatx4 (&acc)[4][4], int n_base,
+                                         const uint16_t* __restrict__ h, uint16_t* out, int S,
+                                         uint16_t* __restrict__ g, int row0, int B, int lane) {
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const int n = n_base + cb * 16 + (lane & 15);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = rb * 16 + 4 * (lane >> 4) + i;
+                uint16_t v = 0;
+                if (row0 + r < B && h[(size_t)(row0 + r) * kHid + n] != 0)
+                    v = to_bf16(acc[rb][cb][i]);
+                if (out) out[r * S + n] = v;
+                if (row0 + r < B) g[(size_t)(row0 + r) * kHid + n] = v;
+            }
+        }
+}
+
+// Gradients with respect to the three hidden layers' pre-activations.
+__global__ void __launch_bounds__(256) mlp_bwd_data_kernel(const MlpBwdArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t bufA[kTile * kS];
+    __shared__ __attribute__((aligned(16))) uint16_t bufB[kTile * kS];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row0 = blockIdx.x * kTile;
+    load_tile<kOutP>(bufA, kSout, a.dz4, row0, a.B);
+    __syncthreads();
+    {
+        floatx4 acc[4][4];
+        tile_gemm<kOutP, 4>(bufA, kSout, a.w4t, wave * 64, acc, lane);
+        grad_out(acc, wave * 64, a.h3, bufB, kS, a.dz3, row0, a.B, lane);
+    }
+    __syncthreads();
+    {
+        floatx4 acc[4][4];
+        tile_gemm<kHid, 4>(bufB, kS, a.w3t, wave * 64, acc, lane);
+        grad_out(acc, wave * 64, a.h2, bufA, kS, a.dz2, row0, a.B, lane);
+    }
+    __syncthreads();
+    {
+        floatx4 acc[4][4];
+        tile_gemm<kHid, 4>(bufA, kS, a.w2t, wave * 64, acc, lane);
+        grad_out(acc, wave * 64, a.h1, nullptr, kS, a.dz1, row0, a.B, lane);
+    }
+}
+
+// Weight gradients dW[n][k] += sum over a chunk of rows of dz[r][n] * h[r][k]
+// (split over row chunks, float32 atomics).  One workgroup: a 64 (n) x 64 (k)
+// tile of one layer over kWgRows rows; both operands are staged transposed in
+// LDS so that fragments are contiguous.
+constexpr int kWgRows = 256;
+constexpr int kWgS = kWgRows + 8;
+
+__global__ void __launch_bounds__(256) mlp_wgrad_kernel(const MlpWgradArgs a) {
+    __shared__ __attribute__((aligned(16))) uint16_t tz[64 * kWgS];  // [n][r]
+    __shared__ __attribute__((aligned(16))) uint16_t th[64 * kWgS];  // [k][r]
+    const WgradTile t = a.tiles[blockIdx.x];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * kWgRows;
+    const LayerGrad& L = a.layers[t.layer];
+    // stage: element (r, n) of dz -> tz[n][r]; (r, k) of h -> th[k][r]
+    for (int i = threadIdx.x; i < kWgRows * 64; i += blockDim.x) {
+        int r = i >> 6, c = i & 63;
+        int row = r0 + r;
+        uint16_t z = 0, h = 0;
+        if (row < a.B) {
+            if (t.n0 + c < L.n_rows) z = L.dz[(size_t)row * L.dz_stride + t.n0 + c];
+            if (t.k0 + c < L.K) h = L.h[(size_t)row * L.K + t.k0 + c];
+        }
+        tz[c * kWgS + r] = z;
+        th[c * kWgS + r] = h;
+    }
+    __syncthreads();
+    // wave w: n rows [16w, 16w+16) of the tile, all 64 k columns
+    floatx4 acc[4];
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < kWgRows; k0 += 32) {
+        bf16x8 fa = frag_lds(tz, kWgS, wave * 16, k0, lane);
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma(fa, frag_lds(th, kWgS, cb * 16, k0, lane), acc[cb]);
+    }
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) {
+        const int k = t.k0 + cb * 16 + (lane & 15);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int n = t.n0 + wave * 16 + 4 * (lane >> 4) + i;
+            if (n < L.n_rows && k < L.K) atomicAdd(&L.gw[(size_t)n * L.K + k], acc[cb][i]);
+        }
+    }
+}
+
+// Bias gradients: db[n] = sum_r dz[r][n]; one workgroup per 64 columns of a
+// layer, rows strided over the four waves.
+__global__ void __launch_bounds__(256) mlp_bgrad_kernel(const MlpWgradArgs a) {
+    __shared__ float part[4][64];
+    const int layer = blockIdx.y;
+    const LayerGrad& L = a.layers[layer];
+    const int n = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int w = threadIdx.x >> 6;
+    float s = 0.0f;
+    if (n < L.n_rows)
+        for (int r = w; r < a.B; r += 4) s += from_bf16(L.dz[(size_t)r * L.dz_stride + n]);
+    part[w][threadIdx.x & 63] = s;
+    __syncthreads();
+    if (w == 0 && n < L.n_rows)
+        L.gb[n] = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+}
+
+// Adam on the float32 master parameters (optional) and refresh of the
+// bfloat16 copies used by the products: w[n][k] and, for layers 2-4, the
+// transposed copy wt[k][n].
+__global__ void mlp_adam_kernel(const MlpAdamArgs a) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kNParams) return;
+    float w = a.params[i];
+    if (a.grad) {
+        const float g = a.grad[i];
+        const float m = a.beta1 * a.m[i] + (1.0f - a.beta1) * g;
+        const float v = a.beta2 * a.v[i] + (1.0f - a.beta2) * (g * g);
+        a.m[i] = m;
+        a.v[i] = v;
+        const float mh = m * a.inv_bc1;
+        const float vh = v * a.inv_bc2;
+        w = w - a.lr * mh / (sqrtf(vh) + a.eps);
+        a.params[i] = w;
+    }
+    const uint16_t h = to_bf16(w);
+    // locate i in the packed layout
+    if (i < kOffB1) {
+        a.w1[i] = h;
+    } else if (i >= kOffW2 && i < kOffB2) {
+        int j = i - kOffW2, n = j / kHid, k = j - n * kHid;
+        a.w2[j] = h;
+        a.w2t[k * kHid + n] = h;
+    } else if (i >= kOffW3 && i < kOffB3) {
+        int j = i - kOffW3, n = j / kHid, k = j - n * kHid;
+        a.w3[j] = h;
+        a.w3t[k * kHid + n] = h;
+    } else if (i >= kOffW4 && i < kOffB4) {
+        int j = i - kOffW4, n = j / kHid, k = j - n * kHid;
+        a.w4[j] = h;
+        a.w4t[k * kOutP + n] = h;
+    }
+}
+
+// State encoding: one thread per state.  Slots hold competitors by
+// position, leader first (equal positions: lower index first); 8 float32
+// features per slot, rounded to bfloat16; zero padding.
+__global__ void encode_kernel(const EncodeArgs a) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.B) return;
+    const int n = min(max(a.n[b], 0), kMaxN);
+    const float* pos = a.pos + (size_t)b * kMaxN;
+    const float* prev = a.prev + (size_t)b * kMaxN;
+    const float* comp = a.comp + (size_t)b * kMaxN * 5;
+    uint16_t* x = a.x + (size_t)b * kIn;
+    for (int j = 0; j < kIn; ++j) x[j] = 0;
+    if (a.slot) for (int r = 0; r < kMaxN; ++r) a.slot[(size_t)b * kMaxN + r] = -1;
+    if (a.target) for (int r = 0; r < kMaxN; ++r) a.target[(size_t)b * kMaxN + r] = 0.0f;
+    const float L = a.track_len;
+    for (int c = 0; c < n; ++c) {
+        const float d = pos[c];
+        int r = 0;
+        for (int i = 0; i < n; ++i) {
+            float di = pos[i];
+            r += (di > d || (di == d && i < c)) ? 1 : 0;
+        }
+        const float lo = comp[c * 5 + 0], hi = comp[c * 5 + 1], rho = comp[c * 5 + 3],
+                    theta = comp[c * 5 + 4];
+        float f[8] = {d / L,           (L - d) / L,     prev[c] / a.c75, (lo + hi) / a.c15,
+                      (hi - lo) / (hi + lo), rho / 0.2f, theta / 2.0f,   1.0f};
+        for (int j = 0; j < 8; ++j) x[r * 8 + j] = to_bf16(f[j]);
+        if (a.slot) a.slot[(size_t)b * kMaxN + r] = c;
+        if (a.target) a.target[(size_t)b * kMaxN + r] = (float)a.probs_in[(size_t)b * kMaxN + c];
+    }
+}
+
+__global__ void fill_f32_kernel(float* __restrict__ p, float v, int n) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// ---------------------------------------------------------------- launchers
+
+hipError_t launch_mlp_fwd(const MlpFwdArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_fwd_kernel, dim3((a.B + kTile - 1) / kTile), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_bwd_data(const MlpBwdArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_bwd_data_kernel, dim3((a.B + kTile - 1) / kTile), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_wgrad(const MlpWgradArgs& a, int n_tiles, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(n_tiles, (a.B + kWgRows - 1) / kWgRows), dim3(256),
+                       0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(mlp_bgrad_kernel, dim3(kHid / 64, 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_mlp_adam(const MlpAdamArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(mlp_adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_encode(const EncodeArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(encode_kernel, dim3((a.B + 63) / 64), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f32(float* p, float v, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_f32_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+}  // namespace bbe

@@ -18,7 +18,7 @@ constexpr uint32_t kTickLimit = 1u << 20;
 // Per-race constants, each rounded once to float32 on the host:
 //   elo = fl(P*lo), espan = fl(P*fl(hi - lo))   free step = elo + espan*u
 //   alpha = fl(1 - rho), beta = fl(fl(2*rho)/L) R_c(d) = alpha + beta*d
-//   theta_bits = bit pattern of theta (theta >= 0, finite)
+//   theta                                        blocked iff gap <= theta
 struct RaceConst {
     float L;
     int n;
@@ -26,13 +26,14 @@ struct RaceConst {
     float espan[kMaxN];
     float alpha[kMaxN];
     float beta[kMaxN];
-    uint32_t theta_bits[kMaxN];
+    float theta[kMaxN];
 };
 
-// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round multiplies
-// the two even counter words by the round multipliers; the high product
-// halves are xored with the odd words and the round key, the low halves
-// become the new odd words, and the key advances by the Weyl increments.
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round forms the
+// 64-bit products of the two even counter words with the round multipliers
+// (one v_mad_u64_u32 each); the high halves are xored with the odd words
+// and the round key, the low halves become the new odd words, and the key
+// advances by the Weyl increments.
 struct U4 {
     uint32_t x, y, z, w;
 };
@@ -41,15 +42,14 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
                                             uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t m0 = 0xD2511F53u, m1 = 0xCD9E8D57u;
-        uint32_t hi0 = __umulhi(m0, c0), lo0 = m0 * c0;
-        uint32_t hi1 = __umulhi(m1, c2), lo1 = m1 * c2;
-        uint32_t n0 = hi1 ^ c1 ^ k0;
-        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
+        uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
         c0 = n0;
-        c1 = lo1;
+        c1 = (uint32_t)p1;
         c2 = n2;
-        c3 = lo0;
+        c3 = (uint32_t)p0;
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
     }
@@ -60,18 +60,5 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 __device__ __forceinline__ float unit24(uint32_t w) {
     return (float)(w >> 8) * 0x1p-24f;
 }
-
-// Ordering key of a gap g = fl(d_i - d_c) as a candidate "competitor ahead"
-// of c.  Non-negative floats order like their bit patterns, so
-//   key = bits(g) - 1   (mod 2^32)
-// maps g > 0 onto [0, 0x7F7FFFFE] in gap order, while g = +0 (a tie, not
-// ahead) becomes 0xFFFFFFFF and every negative g lands above 0x7FFFFFFF:
-// neither can win against a competitor that is really ahead.  For the
-// reversed pair the gap is -g, whose key is bits(g) + 0x7FFFFFFF.  With
-// theta >= 0 finite, "gap <= theta" is exactly key < bits(theta).  A
-// competitor that has finished sits at +inf: its gap keys are >=
-// 0x7F7FFFFF, which never blocks anybody.
-__device__ __forceinline__ uint32_t gap_key_fwd(uint32_t gbits) { return gbits - 1u; }
-__device__ __forceinline__ uint32_t gap_key_rev(uint32_t gbits) { return gbits + 0x7FFFFFFFu; }
 
 }  // namespace bbe

@@ -1,12 +1,14 @@
 // race_kernels.hip -- gfx950 kernels of the race Monte-Carlo (paper Section 3,
 // Eq. 1; Section 6: repeated seeded runs estimate the finish-order PMF).
 //
-// race_mc_kernel<N>: one simulation per lane.  When a lane's simulation ends
-// it takes the next simulation index (lane id + k * grid size), so lanes
-// stay busy although simulations end at different ticks.  Wins are counted
-// in an LDS histogram (one LDS atomic per finished simulation) and flushed
-// with one 64-bit global atomic per competitor per workgroup; competitor-
-// steps are reduced per wave and per workgroup the same way.
+// race_mc_kernel<N>: each wave runs "generations" of 64 simulations, one
+// per lane, all lanes at the same tick (the draws' counter tick is then
+// wave-uniform); a generation ends when all its lanes have finished, and the
+// wave moves on to the next 64 simulation indices of its grid stride.  Wins
+// are counted in an LDS histogram (one LDS atomic per finished simulation)
+// and flushed with one 64-bit global atomic per competitor per workgroup;
+// competitor-steps are summed per simulation from the finishing ticks and
+// reduced per wave and per workgroup the same way.
 #include "kernels.hpp"
 #include "race_sim.hpp"
 
@@ -14,7 +16,17 @@
 
 namespace bbe {
 
-constexpr int kBlock = 256;
+constexpr int kWaves = 4;
+constexpr int kBlock = 64 * kWaves;
+
+template <int N>
+struct BlockLds {
+    static constexpr uint32_t kU = 0;                                      // [wave] u tables
+    static constexpr uint32_t kPar = ((kWaves * N * 256 + 1023) / 1024) * 1024;  // [wave] records
+    static constexpr uint32_t kWins = kPar + kWaves * 1024;               // u32[N]
+    static constexpr uint32_t kSteps = kWins + 128;                        // u64
+    static constexpr uint32_t kBytes = kSteps + 16;
+};
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
@@ -24,70 +36,79 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 template <int N>
 __global__ void __launch_bounds__(kBlock) race_mc_kernel(const SimArgs a) {
-    __shared__ uint32_t s_wins[N];
-    __shared__ unsigned long long s_steps;
+    using Lay = BlockLds<N>;
+    __shared__ __attribute__((aligned(1024))) char smem[Lay::kBytes];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t ucol = Lay::kU + wave * (N * 256) + lane * 4;
+    const uint32_t pbase = Lay::kPar + wave * 1024;
+    uint32_t* s_wins = reinterpret_cast<uint32_t*>(smem + Lay::kWins);
+    unsigned long long* s_steps = reinterpret_cast<unsigned long long*>(smem + Lay::kSteps);
+
+    write_params<N>(smem, pbase, a.rc, lane);
     if (threadIdx.x < N) s_wins[threadIdx.x] = 0u;
-    if (threadIdx.x == 0) s_steps = 0ull;
+    if (threadIdx.x == 0) *s_steps = 0ull;
     __syncthreads();
 
-    const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-    uint64_t j = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+    const float L = a.rc.L;
+    const uint64_t wave_stride = (uint64_t)gridDim.x * kWaves * 64;
     unsigned long long steps = 0ull;
 
-    LaneState<N> st;
-    lane_reset<N>(st, a.d0, a.s0, a.t0);
-    bool active = j < a.n_sims;
-    while (active) {
-        uint8_t* row = a.orders ? a.orders + j * N : nullptr;
-        steps += (unsigned)lane_tick<N>(st, a.rc, a.sim_begin + (uint32_t)j, a.request, a.k0, a.k1,
-                                        row);
-        if (st.nfin >= a.stop_after || st.t - a.t0 >= kTickLimit) {
-            if (st.winner >= 0) atomicAdd(&s_wins[st.winner], 1u);
-            if (row)
-                for (int r = st.nfin; r < N; ++r) row[r] = 0xFF;
-            j += stride;
-            active = j < a.n_sims;
-            lane_reset<N>(st, a.d0, a.s0, a.t0);
-        }
+    for (uint64_t base = ((uint64_t)blockIdx.x * kWaves + wave) * 64; base < a.n_sims;
+         base += wave_stride) {
+        const uint64_t j = base + lane;
+        const bool live = j < a.n_sims;
+        uint8_t* row = (a.orders && live) ? a.orders + j * N : nullptr;
+        run_generation<N>(smem, ucol, pbase, L, a.d0, a.s0, a.id0, a.t0, live,
+                          a.sim_begin + (uint32_t)j, a.request, a.k0, a.k1, a.stop_after, row,
+                          s_wins, steps);
     }
 
     steps = wave_sum_u64(steps);
-    if ((threadIdx.x & 63) == 0) atomicAdd(&s_steps, steps);
+    if (lane == 0) atomicAdd(s_steps, steps);
     __syncthreads();
     if (a.wins && threadIdx.x < N) {
         uint32_t w = s_wins[threadIdx.x];
         if (w) atomicAdd(&a.wins[threadIdx.x], (unsigned long long)w);
     }
-    if (a.steps && threadIdx.x == 0) atomicAdd(a.steps, s_steps);
+    if (a.steps && threadIdx.x == 0) atomicAdd(a.steps, *s_steps);
 }
 
 // One lane advances one simulation until the leader reaches the target.
 template <int N>
 __global__ void __launch_bounds__(64) race_prefix_kernel(const PrefixArgs a) {
-    if (threadIdx.x != 0) return;
-    LaneState<N> st;
-    lane_reset<N>(st, a.d0, a.s0, a.t0);
+    constexpr uint32_t kPar = ((N * 256 + 1023) / 1024) * 1024;
+    __shared__ __attribute__((aligned(1024))) char smem[kPar + 1024];
+    const int lane = threadIdx.x;
+    const uint32_t ucol = lane * 4;
+    write_params<N>(smem, kPar, a.rc, lane);
+    __syncthreads();
+    if (lane != 0) return;
+    Slots<N> sl;
+    slots_reset<N>(sl, a.d0, a.s0, a.id0);
+    uint32_t t = a.t0;
     bool ok = true;
     for (;;) {
-        float lead = st.d[0];
-#pragma unroll
-        for (int c = 1; c < N; ++c) lead = fmaxf(lead, st.d[c]);
-        if (lead >= a.target) break;
-        if (st.t - a.t0 >= kTickLimit) {
+        if (sl.d[N - 1] >= a.target) break;  // slots ascending: the leader is last
+        if (t - a.t0 >= a.max_ticks) break;
+        if (t - a.t0 >= kTickLimit) {
             ok = false;
             break;
         }
-        lane_tick<N>(st, a.rc, a.sim, a.request, a.k0, a.k1, nullptr);
-        if (st.nfin > 0) {
+        uint32_t cross =
+            slots_tick<N>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
+        t += 1;
+        if (cross) {
             ok = false;
             break;
         }
+        slots_restore<N>(sl);
     }
-    *a.tick_out = ok ? st.t : 0xFFFFFFFFu;
+    *a.tick_out = ok ? t : 0xFFFFFFFFu;
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-        a.pos_out[c] = st.d[c];
-        a.prev_out[c] = st.s[c];
+    for (int k = 0; k < N; ++k) {
+        a.pos_out[sl.id[k]] = sl.d[k];
+        a.prev_out[sl.id[k]] = sl.s[k];
     }
 }
 

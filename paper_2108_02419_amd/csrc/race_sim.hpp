@@ -1,24 +1,33 @@
-// race_sim.hpp -- one simulated race per lane (paper Section 3, Eq. 1).
+// race_sim.hpp -- one simulated race per lane, 64 lanes in lockstep
+// (paper Section 3, Eq. 1).
 //
-// A lane holds the positions d[] and previous steps s[] of its simulation
-// in registers (N is a compile-time competitor count, so every competitor
-// index is static).  Finished competitors are parked at +inf, which removes
-// them from the "competitor ahead" search; their update is masked.
+// Layout.  A lane keeps its competitors in N register "slots" sorted by
+// position (ascending; finished competitors are parked at +inf at the
+// top).  Slot k holds the position d[k], the previous step s[k] and the
+// index id[k] of the competitor that occupies it, which locates its draw
+// and its parameter record in LDS.  Slots are kept in
+// (position, competitor index) order, so the competitor ahead of slot k is
+// the first slot above it with a larger position -- slot k+1 unless
+// positions are equal -- and the query of Eq. 1 costs O(1) per competitor
+// instead of a scan over all pairs.
 //
-// One tick (absolute tick t -> t+1), all from the start-of-tick state:
-//   1. draws: Philox4x32-10(key = seed, ctr = (t, sim, request, b)) for
-//      blocks b = 0 .. ceil(N/4)-1; competitor c takes word c&3 of block
-//      c>>2 and u = (w >> 8) * 2^-24;
-//   2. competitor ahead: over all pairs, the smallest positive gap
-//      fl(d_i - d_c) and the previous step of that competitor, the lowest
-//      index winning equal gaps (pairs are visited in ascending index order
-//      and only a strictly smaller key replaces the current one);
+// One tick (all 64 lanes at the same absolute tick t):
+//   1. draws in competitor order: Philox4x32-10(key = seed,
+//      ctr = (t, sim, request, b)) for blocks b = 0 .. ceil(N/4)-1;
+//      competitor c takes word c&3 of block c>>2, u = (w >> 8) * 2^-24; the
+//      draws go to the lane's column of an LDS table and each slot reads
+//      the draw of its own competitor;
+//   2. competitor ahead: the running competitor with the smallest position
+//      greater than d_c (lowest index among equal positions); gap =
+//      fl(d_ahead - d_c), +inf if nobody is ahead;
 //   3. Eq. 1: R = alpha + beta*d; free: S = R*(elo + espan*u); blocked
 //      (gap <= theta): S = R*min(s_c, s_ahead);
-//   4. synchronous update d += S, s = S for running competitors; a
+//   4. synchronous update d += S, s = S of the running competitors; a
 //      competitor whose new position reaches L crosses the line;
 //   5. this tick's finishers are ranked after the earlier ones, among
-//      themselves by the fraction fl((L - d_old)/S), then by index.
+//      themselves by the fraction fl((L - d_old)/S), then by index, and are
+//      parked at +inf;
+//   6. bubble passes restore the slot order.
 #pragma once
 
 #include "race_common.hpp"
@@ -26,129 +35,237 @@
 namespace bbe {
 
 template <int N>
-struct LaneState {
+struct Slots {
     float d[N];
     float s[N];
-    uint32_t t;
-    int nfin;
-    int winner;
+    uint32_t id[N];
 };
 
-template <int N>
-__device__ __forceinline__ void lane_reset(LaneState<N>& st, const float* __restrict__ d0,
-                                           const float* __restrict__ s0, uint32_t t0) {
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-        st.d[c] = d0[c];
-        st.s[c] = s0[c];
-    }
-    st.t = t0;
-    st.nfin = 0;
-    st.winner = -1;
+__device__ __forceinline__ float lds_f32(const char* smem, uint32_t off) {
+    return *reinterpret_cast<const float*>(smem + off);
 }
 
-// Advance one tick.  Returns the number of competitors that stepped.
-// `order_row` (may be null) receives the finishers of this tick at their
-// ranks.
+__device__ __forceinline__ void lds_st_f32(char* smem, uint32_t off, float v) {
+    *reinterpret_cast<float*>(smem + off) = v;
+}
+
+// Writes the parameter records of a race into a wave's record block:
+// record c = (elo, espan, alpha, beta, theta, -, -, -) at pbase + 32*c.
 template <int N>
-__device__ __forceinline__ int lane_tick(LaneState<N>& st, const RaceConst& rc, uint32_t sim,
-                                         uint32_t request, uint32_t k0, uint32_t k1,
-                                         uint8_t* __restrict__ order_row) {
-    // 1. draws
-    float u[N];
+__device__ __forceinline__ void write_params(char* smem, uint32_t pbase, const RaceConst& rc,
+                                            int lane) {
+    if (lane < N) {
+        float4* rec = reinterpret_cast<float4*>(smem + pbase + lane * 32);
+        rec[0] = make_float4(rc.elo[lane], rc.espan[lane], rc.alpha[lane], rc.beta[lane]);
+        rec[1] = make_float4(rc.theta[lane], 0.0f, 0.0f, 0.0f);
+    }
+}
+
+// Loads an initial state already in slot order (positions ascending, equal
+// positions by competitor index).
+template <int N>
+__device__ __forceinline__ void slots_reset(Slots<N>& sl, const float* __restrict__ d0,
+                                            const float* __restrict__ s0,
+                                            const uint8_t* __restrict__ id0) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        sl.d[k] = d0[k];
+        sl.s[k] = s0[k];
+        sl.id[k] = id0[k];
+    }
+}
+
+// Steps 1-4 for one lane.  `ucol` is the byte offset of this lane's column
+// of the draw table (competitor c's draw at ucol + 256*c), `pbase` that of
+// the wave's parameter records.  Returns the bit mask of slots that crossed
+// the line (their d[] still holds the start-of-tick position).
+template <int N>
+__device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_t ucol,
+                                               uint32_t pbase, float L, uint32_t t,
+                                               uint32_t sim, uint32_t request, uint32_t k0,
+                                               uint32_t k1) {
+    // 1. draws, competitor order, into this lane's column
 #pragma unroll
     for (int b = 0; b < (N + 3) / 4; ++b) {
-        U4 w = philox4x32_10(st.t, sim, request, (uint32_t)b, k0, k1);
-        if (4 * b + 0 < N) u[4 * b + 0] = unit24(w.x);
-        if (4 * b + 1 < N) u[4 * b + 1] = unit24(w.y);
-        if (4 * b + 2 < N) u[4 * b + 2] = unit24(w.z);
-        if (4 * b + 3 < N) u[4 * b + 3] = unit24(w.w);
+        U4 w = philox4x32_10(t, sim, request, (uint32_t)b, k0, k1);
+        if (4 * b + 0 < N) lds_st_f32(smem, ucol + (4 * b + 0) * 256, unit24(w.x));
+        if (4 * b + 1 < N) lds_st_f32(smem, ucol + (4 * b + 1) * 256, unit24(w.y));
+        if (4 * b + 2 < N) lds_st_f32(smem, ucol + (4 * b + 2) * 256, unit24(w.z));
+        if (4 * b + 3 < N) lds_st_f32(smem, ucol + (4 * b + 3) * 256, unit24(w.w));
     }
 
-    // 2. competitor ahead
-    uint32_t best[N];
-    float s_ahead[N];
+    // 2. competitor ahead.  Slots are in (position, index) order, so with
+    //    distinct positions it is the next slot; where positions are equal
+    //    it is the first slot of the next higher position, found by a pass
+    //    from the top (that slot is the lowest index of its group).
+    float ahead_d[N], s_ahead[N];
+    bool tie = false;
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-        best[c] = 0xFFFFFFFFu;
-        s_ahead[c] = 0.0f;
+    for (int k = 0; k < N - 1; ++k) {
+        ahead_d[k] = sl.d[k + 1];
+        s_ahead[k] = sl.s[k + 1];
+        tie |= (sl.d[k + 1] == sl.d[k]) && (sl.d[k] < L);
     }
+    ahead_d[N - 1] = __builtin_inff();
+    s_ahead[N - 1] = 0.0f;
+    if (tie) {
+        float nd = __builtin_inff(), ns = 0.0f;  // nearest above the slot just visited
 #pragma unroll
-    for (int a = 0; a < N; ++a) {
-#pragma unroll
-        for (int b = a + 1; b < N; ++b) {
-            uint32_t g = __float_as_uint(st.d[b] - st.d[a]);
-            uint32_t ka = gap_key_fwd(g);
-            uint32_t kb = gap_key_rev(g);
-            if (ka < best[a]) {
-                best[a] = ka;
-                s_ahead[a] = st.s[b];
-            }
-            if (kb < best[b]) {
-                best[b] = kb;
-                s_ahead[b] = st.s[a];
-            }
+        for (int k = N - 2; k >= 0; --k) {
+            bool gt = sl.d[k + 1] > sl.d[k];
+            nd = gt ? sl.d[k + 1] : nd;
+            ns = gt ? sl.s[k + 1] : ns;
+            ahead_d[k] = nd;
+            s_ahead[k] = ns;
         }
     }
 
-    // 3. Eq. 1
-    float S[N];
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-        float R = rc.alpha[c] + rc.beta[c] * st.d[c];
-        float x = rc.elo[c] + rc.espan[c] * u[c];
-        float s_free = R * x;
-        float s_blocked = R * fminf(st.s[c], s_ahead[c]);
-        S[c] = (best[c] < rc.theta_bits[c]) ? s_blocked : s_free;
-    }
-
-    // 4. synchronous update; crossers keep their start-of-tick position
-    //    until they are ranked
-    const float L = rc.L;
+    // 3. Eq. 1 and 4. synchronous update
     uint32_t cross = 0;
-    int nrun = 0;
 #pragma unroll
-    for (int c = 0; c < N; ++c) {
-        bool run = st.d[c] < L;
-        float dn = st.d[c] + S[c];
+    for (int k = 0; k < N; ++k) {
+        const uint32_t id = sl.id[k];
+        const float u = lds_f32(smem, ucol + (id << 8));
+        const uint32_t po = pbase + (id << 5);
+        const float4 p = *reinterpret_cast<const float4*>(smem + po);
+        const float theta = lds_f32(smem, po + 16);
+        const float d = sl.d[k];
+        float R = p.z + p.w * d;
+        float x = p.x + p.y * u;
+        float s_free = R * x;
+        float s_blocked = R * fminf(sl.s[k], s_ahead[k]);
+        float gap = ahead_d[k] - d;  // +inf when nobody is ahead
+        float S = (gap <= theta) ? s_blocked : s_free;
+        bool run = d < L;
+        float dn = d + S;
         bool cr = run && (dn >= L);
-        cross |= (uint32_t)cr << c;
-        st.d[c] = (run && !cr) ? dn : st.d[c];
-        st.s[c] = run ? S[c] : st.s[c];
-        nrun += run ? 1 : 0;
+        cross |= cr ? (1u << k) : 0u;
+        sl.d[k] = (run && !cr) ? dn : d;
+        sl.s[k] = run ? S : sl.s[k];
     }
-    st.t += 1;
+    return cross;
+}
 
-    // 5. rank this tick's finishers
-    if (cross) {
-        if (cross & (cross - 1u)) {
-            float fr[N];
+// Step 5: rank this tick's finishers (slot mask `cross`) after the `nfin`
+// earlier ones, record them, park them at +inf.  Returns the number ranked.
+template <int N>
+__device__ __forceinline__ int slots_finish(Slots<N>& sl, uint32_t cross, float L, int nfin,
+                                            int& winner, uint8_t* __restrict__ row) {
+    float fr[N];
+    const bool multi = (cross & (cross - 1u)) != 0u;
+    if (multi) {
 #pragma unroll
-            for (int c = 0; c < N; ++c)
-                if ((cross >> c) & 1u) fr[c] = (L - st.d[c]) / st.s[c];
-#pragma unroll
-            for (int c = 0; c < N; ++c) {
-                if (!((cross >> c) & 1u)) continue;
-                int r = st.nfin;
-#pragma unroll
-                for (int i = 0; i < N; ++i) {
-                    if (i == c || !((cross >> i) & 1u)) continue;
-                    if (fr[i] < fr[c] || (fr[i] == fr[c] && i < c)) ++r;
-                }
-                if (r == 0) st.winner = c;
-                if (order_row) order_row[r] = (uint8_t)c;
-            }
-        } else {
-            int c = __builtin_ctz(cross);
-            if (st.nfin == 0) st.winner = c;
-            if (order_row) order_row[st.nfin] = (uint8_t)c;
-        }
-        st.nfin += __builtin_popcount(cross);
-#pragma unroll
-        for (int c = 0; c < N; ++c)
-            if ((cross >> c) & 1u) st.d[c] = __builtin_inff();
+        for (int k = 0; k < N; ++k)
+            if ((cross >> k) & 1u) fr[k] = (L - sl.d[k]) / sl.s[k];
     }
-    return nrun;
+    int ranked = 0;
+    uint32_t rem = cross;
+    while (rem) {
+        int bk = -1;
+        float bf = 0.0f;
+        uint32_t bid = 32u;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            if (!((rem >> k) & 1u)) continue;
+            uint32_t idk = sl.id[k];
+            float f = multi ? fr[k] : 0.0f;
+            bool better = (bk < 0) || (f < bf) || (f == bf && idk < bid);
+            bk = better ? k : bk;
+            bf = better ? f : bf;
+            bid = better ? idk : bid;
+        }
+        int r = nfin + ranked;
+        if (r == 0) winner = (int)bid;
+        if (row) row[r] = (uint8_t)bid;
+        ++ranked;
+        rem &= ~(1u << bk);
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if ((cross >> k) & 1u) sl.d[k] = __builtin_inff();
+    return ranked;
+}
+
+// Order key of a slot: position first (non-negative floats and +inf order
+// like their bit patterns), then the competitor index.
+__device__ __forceinline__ uint64_t slot_key(float d, uint32_t id) {
+    return ((uint64_t)__float_as_uint(d) << 32) | id;
+}
+
+// Step 6: one bubble pass restoring (position, index) order.  Each
+// compare-exchange is branch-free (unsigned min/max of the position bit
+// patterns, selects of the rest) and is skipped when no lane of the wave
+// needs it.  Returns true (wave-uniform) if any lane swapped.  Lanes whose
+// simulation has ended are sorted too; their slots are no longer read.
+template <int N>
+__device__ __forceinline__ bool slots_bubble(Slots<N>& sl) {
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < N - 1; ++k) {
+        bool sw = slot_key(sl.d[k], sl.id[k]) > slot_key(sl.d[k + 1], sl.id[k + 1]);
+        if (__builtin_amdgcn_ballot_w64(sw)) {
+            uint32_t a = __float_as_uint(sl.d[k]), b = __float_as_uint(sl.d[k + 1]);
+            float s0 = sw ? sl.s[k + 1] : sl.s[k];
+            float s1 = sw ? sl.s[k] : sl.s[k + 1];
+            uint32_t i0 = sw ? sl.id[k + 1] : sl.id[k];
+            uint32_t i1 = sw ? sl.id[k] : sl.id[k + 1];
+            sl.d[k] = __uint_as_float(a < b ? a : b);
+            sl.d[k + 1] = __uint_as_float(a < b ? b : a);
+            sl.s[k] = s0;
+            sl.s[k + 1] = s1;
+            sl.id[k] = i0;
+            sl.id[k + 1] = i1;
+            any = true;
+        }
+    }
+    return any;
+}
+
+// Step 6 in full: passes until no lane of the wave swaps (the usual tick
+// needs one pass that swaps and one that confirms).
+template <int N>
+__device__ __forceinline__ void slots_restore(Slots<N>& sl) {
+    while (slots_bubble<N>(sl)) {
+    }
+}
+
+
+// One generation: up to 64 simulations of one race from one state, one per
+// lane, in lockstep from tick t0.  `live` marks the lanes that hold a
+// simulation (index `sim`); `row` (or null) receives its finish order.
+// Winners go to the LDS histogram `hist`; competitor-steps add to `steps`.
+template <int N>
+__device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t pbase,
+                                               float L, const float* __restrict__ d0,
+                                               const float* __restrict__ s0,
+                                               const uint8_t* __restrict__ id0, uint32_t t0,
+                                               bool live, uint32_t sim, uint32_t request,
+                                               uint32_t k0, uint32_t k1, int stop_after,
+                                               uint8_t* __restrict__ row, uint32_t* hist,
+                                               unsigned long long& steps) {
+    Slots<N> sl;
+    slots_reset<N>(sl, d0, s0, id0);
+    uint32_t t = t0;
+    int nfin = 0, winner = -1;
+    while (__builtin_amdgcn_ballot_w64(live)) {
+        if (live) {
+            uint32_t cross = slots_tick<N>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
+            if (cross) {
+                int k = slots_finish<N>(sl, cross, L, nfin, winner, row);
+                nfin += k;
+                steps += (unsigned long long)k * (t + 1 - t0);
+            }
+            if (nfin >= stop_after || t + 1 - t0 >= kTickLimit) {
+                if (winner >= 0) atomicAdd(&hist[winner], 1u);
+                if (row)
+                    for (int r = nfin; r < N; ++r) row[r] = 0xFF;
+                steps += (unsigned long long)(N - nfin) * (t + 1 - t0);
+                live = false;
+            }
+        }
+        t += 1;
+        slots_restore<N>(sl);
+    }
 }
 
 }  // namespace bbe

@@ -130,3 +130,19 @@ def query_race(cfg: dict = CFG_QUERY) -> dict:
     rng = np.random.default_rng(cfg["seed"])
     comp = competitor_params(rng, cfg["n"], cfg["dt"])
     return dict(comp=comp, L=TRACK_LEN, seed=cfg["seed"], real_request=cfg["real_request"])
+
+
+SURROGATE_LAYERS = [(256, 160), (256, 256), (256, 256), (20, 256)]
+
+
+def surrogate_init(seed: int = 4) -> np.ndarray:
+    """Initial surrogate parameters (packed W1, b1, ..., W4, b4, float32):
+    weights uniform in +-sqrt(6/fan_in) (He-uniform for ReLU layers; the
+    output layer uses +-sqrt(1/fan_in)), biases zero."""
+    rng = np.random.default_rng([seed, 0x5EED])
+    parts = []
+    for i, (n, k) in enumerate(SURROGATE_LAYERS):
+        bound = np.sqrt((1.0 if i == 3 else 6.0) / k)
+        parts.append(rng.uniform(-bound, bound, size=n * k))
+        parts.append(np.zeros(n))
+    return np.concatenate(parts).astype(np.float32)

@@ -85,3 +85,32 @@ def test_race_sim_rejects_before_device_work(L):
 def test_last_error_cleared_on_success(L):
     _bbe.Race(np.array(GOOD, np.float32), 2000.0)
     assert L.bbe_last_error().decode() == ""
+
+
+def test_batch_plan_rejects_before_device_work(L):
+    race = _bbe.Race(np.array(GOOD, np.float32), 2000.0)
+    null = ctypes.c_void_p()
+    out = ctypes.c_void_p()
+    fake_out = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    bad = [
+        [(race, None, 0, 0, 0, 0)],                 # n_sims = 0
+        [(race, None, 0, 10, 0, 4)],                # stop_after > n
+        [(race, None, 2**32 - 5, 10, 0, 0)],        # range beyond 2^32
+        [(race, (3, np.array([0, 1, 2001], np.float32), np.ones(3, np.float32)), 0, 10, 0, 0)],
+    ]
+    for specs in bad:
+        arr, keep = _bbe._request_array(specs)
+        rc = L.bbe_batch_plan_create(arr, len(specs), 1, fake_out, null, null, 0, null,
+                                     ctypes.byref(out))
+        assert rc == _bbe.EINVAL, specs
+        assert L.bbe_last_error().decode()
+    arr, keep = _bbe._request_array([(race, None, 0, 10, 0, 0)])
+    assert L.bbe_batch_plan_create(arr, 0, 1, fake_out, null, null, 0, null,
+                                   ctypes.byref(out)) == _bbe.EINVAL
+    assert L.bbe_batch_plan_create(arr, 1, 1, null, null, null, 0, null,
+                                   ctypes.byref(out)) == _bbe.EINVAL
+    assert L.bbe_batch_plan_launch(None, None) == _bbe.EINVAL
+    rc = L.bbe_prefix_batch(arr, np.zeros(1, np.uint32).ctypes.data,
+                            np.array([5000.0], np.float32).ctypes.data, 1, 1, fake_out,
+                            fake_out, fake_out, null)
+    assert rc == _bbe.EINVAL  # target beyond the track

@@ -1,0 +1,137 @@
+"""GPU parity of the batched path (persistent kernel in a captured graph):
+per-request win counts, probabilities and competitor-steps equal the CPU
+oracle's; batched equals individual calls; graph replays repeat exactly; the
+batched in-play state generator equals the oracle's."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, require_gpu
+from paper_2108_02419_amd import _bbe, api, inputs
+from paper_2108_02419_amd._bbe import BatchPlan, Race
+
+pytestmark = pytest.mark.gpu
+L = inputs.TRACK_LEN
+SEED = 3
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _oracle_states(orc, reqs):
+    return [orc.race_prefix(r.comp, L, SEED, r.prefix_request, 0, r.target) for r in reqs]
+
+
+def _run_plan(torch, specs, seed, autotune=True):
+    n = len(specs)
+    wins = torch.zeros((n, 20), dtype=torch.int64, device="cuda")
+    probs = torch.zeros((n, 20), dtype=torch.float64, device="cuda")
+    steps = torch.zeros(1, dtype=torch.int64, device="cuda")
+    plan = BatchPlan(specs, seed, wins, probs, steps, autotune=autotune)
+    plan.launch()
+    torch.cuda.synchronize()
+    return plan, wins, probs, steps
+
+
+def test_batch_matches_oracle(torch, orc):
+    reqs = inputs.batch_requests(n_requests=48)
+    states = _oracle_states(orc, reqs)
+    races = [Race(r.comp, L) for r in reqs]
+    rng = np.random.default_rng(7)
+    specs, exp_w, exp_s = [], [], 0
+    for i, (r, st, race) in enumerate(zip(reqs, states, races)):
+        n_sims = int(min(r.n_sims, 700))
+        stop = int(rng.choice([0, 1, max(1, r.n // 2)]))
+        begin = int(rng.integers(0, 1000))
+        specs.append((race, st, begin, n_sims, r.index, stop))
+        _, w, s = orc.race_sim(r.comp, L, n_sims, SEED, request=r.index, state=st,
+                               sim_begin=begin, stop_after=stop or r.n, want_orders=False,
+                               threads=8)
+        exp_w.append(w)
+        exp_s += s
+    announce(f"batch of {len(specs)} requests")
+    plan, wins, probs, steps = _run_plan(torch, specs, SEED)
+    W = wins.cpu().numpy()
+    P = probs.cpu().numpy()
+    for i, r in enumerate(reqs):
+        np.testing.assert_array_equal(W[i, :r.n].astype(np.uint64), exp_w[i])
+        assert (W[i, r.n:] == 0).all()
+        np.testing.assert_array_equal(P[i, :r.n], orc.win_probs(exp_w[i]))
+        assert (P[i, r.n:] == 0).all()
+    assert int(steps.item()) == exp_s
+    info = plan.info()
+    assert info["waves_per_block"] in (1, 2, 4) and info["n_items"] >= len(specs)
+
+
+def test_batch_equals_individual_calls_and_replays(torch, orc):
+    reqs = inputs.batch_requests(n_requests=24)
+    states = _oracle_states(orc, reqs)
+    races = [Race(r.comp, L) for r in reqs]
+    specs = [(race, st, 0, int(min(r.n_sims, 2000)), r.index, 0)
+             for r, st, race in zip(reqs, states, races)]
+    plan, wins, probs, steps = _run_plan(torch, specs, SEED, autotune=False)
+    first_w, first_p, first_s = wins.clone(), probs.clone(), steps.clone()
+    for i, (race, st, b, n_sims, req, _) in enumerate(specs):
+        out = api.mc(race, n_sims, SEED, request=req, state=st, sim_begin=b)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out["wins"].cpu().numpy(), first_w[i, :race.n].cpu().numpy())
+    # replays of the captured graph, with eager work in between
+    for k in range(4):
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        plan.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(wins, first_w) and torch.equal(probs, first_p)
+        assert torch.equal(steps, first_s), k
+        del junk
+
+
+def test_prefix_batch_matches_oracle(torch, orc):
+    reqs = inputs.batch_requests(n_requests=150)
+    races = [Race(r.comp, L) for r in reqs]
+    specs = [(race, None, 0, 1, r.prefix_request, 0) for r, race in zip(reqs, races)]
+    n = len(specs)
+    tick = torch.zeros(n, dtype=torch.int32, device="cuda")
+    pos = torch.zeros((n, 20), dtype=torch.float32, device="cuda")
+    prev = torch.zeros((n, 20), dtype=torch.float32, device="cuda")
+    _bbe.prefix_batch(specs, np.zeros(n, np.uint32), [r.target for r in reqs], SEED, tick, pos,
+                      prev)
+    torch.cuda.synchronize()
+    T, Pp, Pv = tick.cpu().numpy().view(np.uint32), pos.cpu().numpy(), prev.cpu().numpy()
+    for i, r in enumerate(reqs):
+        ot, op, oq = orc.race_prefix(r.comp, L, SEED, r.prefix_request, 0, r.target)
+        assert T[i] == ot
+        np.testing.assert_array_equal(Pp[i, :r.n], op)
+        np.testing.assert_array_equal(Pv[i, :r.n], oq)
+
+
+def test_full_batch_workload(torch, orc):
+    """The 4096-request workload as the benchmark runs it: states from the
+    GPU generator, one autotuned plan; every row tallies exactly its
+    simulations, and sampled requests equal the oracle."""
+    reqs = inputs.batch_requests()
+    announce(f"full batch: {len(reqs)} requests, {sum(r.n_sims for r in reqs)} sims")
+    races = [Race(r.comp, L) for r in reqs]
+    n = len(reqs)
+    tick = torch.zeros(n, dtype=torch.int32, device="cuda")
+    pos = torch.zeros((n, 20), dtype=torch.float32, device="cuda")
+    prev = torch.zeros((n, 20), dtype=torch.float32, device="cuda")
+    _bbe.prefix_batch([(race, None, 0, 1, r.prefix_request, 0) for r, race in zip(reqs, races)],
+                      np.zeros(n, np.uint32), [r.target for r in reqs], SEED, tick, pos, prev)
+    torch.cuda.synchronize()
+    T, Pp, Pv = tick.cpu().numpy().view(np.uint32), pos.cpu().numpy(), prev.cpu().numpy()
+    assert (T != 0xFFFFFFFF).all()
+    states = [(int(T[i]), Pp[i, :r.n].copy(), Pv[i, :r.n].copy()) for i, r in enumerate(reqs)]
+    specs = [(race, st, 0, r.n_sims, r.index, 0) for r, st, race in zip(reqs, states, races)]
+    plan, wins, probs, steps = _run_plan(torch, specs, SEED)
+    W = wins.cpu().numpy()
+    np.testing.assert_array_equal(W.sum(axis=1), [r.n_sims for r in reqs])
+    rng = np.random.default_rng(1)
+    for i in rng.choice(n, 6, replace=False):
+        r = reqs[i]
+        ost = orc.race_prefix(r.comp, L, SEED, r.prefix_request, 0, r.target)
+        assert ost[0] == states[i][0]
+        np.testing.assert_array_equal(ost[1], states[i][1])
+        _, w, _ = orc.race_sim(r.comp, L, r.n_sims, SEED, request=r.index, state=ost,
+                               want_orders=False, threads=8)
+        np.testing.assert_array_equal(W[i, :r.n].astype(np.uint64), w)

@@ -1,0 +1,132 @@
+"""GPU parity of the surrogate kernels against the float64 reference
+(oracle/mlp.py) on the same seeded inputs: the encoder bit for bit, the
+forward pass and the gradients within tolerances derived from bfloat16
+operands with float32 accumulation, Adam within 1e-6 relative."""
+import numpy as np
+import pytest
+
+from gpu_util import announce, require_gpu
+from oracle import mlp as ref
+from paper_2108_02419_amd import _bbe, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    return require_gpu()
+
+
+def _features(rng, B):
+    """Random bfloat16-exact feature rows, valid-slot counts and targets."""
+    X = ref.bf16(rng.normal(0, 1, size=(B, ref.IN)))
+    n = rng.integers(1, 21, size=B).astype(np.int32)
+    n[: min(B, 3)] = [20, 1, 7][: min(B, 3)]
+    T = rng.random((B, ref.OUT)) * (np.arange(ref.OUT)[None, :] < n[:, None])
+    T /= T.sum(axis=1, keepdims=True)
+    return X, n, T.astype(np.float32)
+
+
+def _bits(torch, X):
+    u = np.asarray(X, np.float32).view(np.uint32) >> 16
+    return torch.tensor(u.astype(np.uint16).view(np.int16), device="cuda")
+
+
+def test_forward_matches_reference(torch):
+    rng = np.random.default_rng(0)
+    params = inputs.surrogate_init(4)
+    for B in [1, 63, 64, 200]:  # one tile, ragged tails, several tiles
+        announce(f"mlp forward B={B}")
+        X, n, _ = _features(rng, B)
+        net = _bbe.Mlp(params, max_batch=256)
+        xt, nt = _bits(torch, X), torch.tensor(n, device="cuda")
+        probs = torch.empty((B, 20), dtype=torch.float32, device="cuda")
+        ent = torch.empty(B, dtype=torch.float32, device="cuda")
+        logits = torch.empty((B, 32), dtype=torch.float32, device="cuda")
+        net.forward(xt, nt, probs, ent, logits)
+        torch.cuda.synchronize()
+        z, q, _ = ref.forward(params.astype(np.float64), X, n)
+        zg = logits.cpu().numpy()[:, :20]
+        mask = np.arange(20)[None, :] < n[:, None]
+        scale = np.abs(z[mask]).max()
+        assert np.abs(zg[mask] - z[mask]).max() <= 2e-2 * scale + 1e-3
+        assert np.isneginf(zg[~mask]).all()
+        np.testing.assert_allclose(probs.cpu().numpy(), q, atol=2e-3)
+        np.testing.assert_allclose(ent.cpu().numpy(), ref.entropy(q), atol=5e-3)
+
+
+def test_gradients_match_reference(torch):
+    rng = np.random.default_rng(1)
+    params = inputs.surrogate_init(4)
+    B = 300
+    X, n, T = _features(rng, B)
+    net = _bbe.Mlp(params, max_batch=512)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    grad = torch.empty(_bbe.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+    net.loss_grad(_bits(torch, X), torch.tensor(n, device="cuda"),
+                  torch.tensor(T, device="cuda"), loss, grad)
+    torch.cuda.synchronize()
+    l_ref, g_ref = ref.loss_and_grad(params.astype(np.float64), X, n, T)
+    assert abs(loss.item() - l_ref) <= 1e-4 * abs(l_ref)
+    g = grad.cpu().numpy().astype(np.float64)
+    G, R = ref.unpack(g), ref.unpack(g_ref)
+    for name in G:
+        err = np.linalg.norm(G[name] - R[name]) / max(np.linalg.norm(R[name]), 1e-30)
+        assert err <= 1e-3, (name, err)
+
+
+def test_adam_matches_reference(torch):
+    rng = np.random.default_rng(2)
+    params = inputs.surrogate_init(4)
+    net = _bbe.Mlp(params, max_batch=8)
+    p = params.astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    for step in range(1, 4):
+        g = rng.normal(0, 1e-3, size=p.shape)
+        p, m, v = ref.adam(p, g, m, v, step, 1e-3)
+        net.adam_step(1e-3, grad=torch.tensor(g.astype(np.float32), device="cuda"))
+    torch.cuda.synchronize()
+    got = net.params().astype(np.float64)
+    np.testing.assert_allclose(got, p, rtol=1e-6, atol=1e-9)
+
+
+def test_encoder_bit_exact(torch):
+    reqs = inputs.surrogate_states(64)
+    import oracle
+    B = len(reqs)
+    comp = np.zeros((B, 20, 5), np.float32)
+    pos = np.zeros((B, 20), np.float32)
+    prev = np.zeros((B, 20), np.float32)
+    n = np.array([r.n for r in reqs], np.int32)
+    for i, r in enumerate(reqs):
+        comp[i, :r.n] = r.comp
+        t, p, q = oracle.race_prefix(r.comp, inputs.TRACK_LEN, 4, r.prefix_request, 0, r.target)
+        pos[i, :r.n], prev[i, :r.n] = p, q
+    pos[5, :3] = pos[5, 3]  # exact ties exercise the slot order
+    X, slot = ref.encode(comp, n, pos, prev, inputs.TRACK_LEN, 0.1)
+    x = torch.empty((B, 160), dtype=torch.int16, device="cuda")
+    s = torch.empty((B, 20), dtype=torch.int32, device="cuda")
+    _bbe.encode_states(torch.tensor(comp, device="cuda"), torch.tensor(n, device="cuda"),
+                       torch.tensor(pos, device="cuda"), torch.tensor(prev, device="cuda"),
+                       inputs.TRACK_LEN, 0.1, x, s)
+    torch.cuda.synchronize()
+    want = (ref.bf16(X).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+    np.testing.assert_array_equal(x.cpu().numpy().view(np.uint16), want)
+    np.testing.assert_array_equal(s.cpu().numpy(), slot)
+
+
+def test_training_reduces_loss(torch):
+    rng = np.random.default_rng(3)
+    params = inputs.surrogate_init(4)
+    B = 512
+    X, n, T = _features(rng, B)
+    net = _bbe.Mlp(params, max_batch=B)
+    xt, nt, tt = _bits(torch, X), torch.tensor(n, device="cuda"), torch.tensor(T, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    losses = []
+    for _ in range(60):
+        net.train_step(xt, nt, tt, 1e-3, loss)
+        losses.append(loss.item())
+    ent = float(np.mean([-(t[t > 0] * np.log(t[t > 0])).sum() for t in T]))
+    assert losses[-1] < losses[0] - 0.5 * (losses[0] - ent), (losses[0], losses[-1], ent)
