@@ -9,10 +9,14 @@ seeded and synthetic (paper_2108_02419_amd/inputs.py); every step uses a
 new Monte-Carlo seed.
 
 Prints ONE JSON line.  `value` is simulations per second; the roofline
-object prices the Monte-Carlo kernel against the VALU peak of the chip
-(256 CUs x 64 lanes x 2.4 GHz, full-rate lane operations) using the
+object prices the Monte-Carlo kernel against the vector-ALU peak of the chip
+(256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz lane-operations per second) using the
 algorithmic cost per competitor-step; the cpu_baseline object times the
-CPU oracle on a bounded sample of the same workload.
+CPU oracle on a bounded sample of the same workload.  Two more objects
+measure the other workloads of the path: `batch` (4096 uneven in-play
+requests in one graph-captured persistent launch) and `surrogate` (queries
+per second of the surrogate network against Monte-Carlo at 10^4 simulations
+per query, on the same in-play state).
 """
 from __future__ import annotations
 
@@ -26,11 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic VALU work per competitor-step, in full-rate lane-operation
-# equivalents: a quarter of one Philox4x32-10 block (the draw), the
-# competitor-ahead query with a maintained order, Eq. 1 and the update.
-ALGO_OPS_PER_COMPETITOR_STEP = 48.0
-VALU_PEAK_OPS = 256 * 64 * 2.4e9  # lane-ops/s: CUs x lanes x clock
+# Algorithmic vector work per competitor-step, in 32-bit lane-operation
+# equivalents (a 32x32->64 product counted 3): a quarter of one
+# Philox4x32-10 block plus its conversion (28), the competitor-ahead query
+# with a maintained order (3), Eq. 1 (9), the update and finish test (4).
+ALGO_OPS_PER_COMPETITOR_STEP = 44.0
+VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9  # lane-ops/s: CUs x SIMDs x lanes x clock
 
 
 def cpu_baseline(c, target_s: float = 12.0):
@@ -62,6 +67,9 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--stop-after", type=int, default=None,
                     help="finishers to resolve per simulation (default: all 20)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -169,10 +177,129 @@ def main() -> int:
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
                      "ops_per_competitor_step": ALGO_OPS_PER_COMPETITOR_STEP},
     }
+    if not args.no_batch:
+        line["batch"] = batch_leg(args.batch_steps)
+    if not args.no_surrogate:
+        line["surrogate"] = surrogate_leg()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(line), flush=True)
     return 0
+
+
+def batch_leg(steps: int):
+    """4096 uneven in-play requests (states from the GPU generator), one
+    autotuned plan, `steps` timed graph launches."""
+    import numpy as np
+    import torch
+
+    from paper_2108_02419_amd import _bbe, inputs
+    reqs = inputs.batch_requests()
+    races = [_bbe.Race(r.comp, inputs.TRACK_LEN) for r in reqs]
+    n = len(reqs)
+    dev = torch.device("cuda", 0)
+    tick = torch.empty(n, dtype=torch.int32, device=dev)
+    pos = torch.empty((n, 20), dtype=torch.float32, device=dev)
+    prev = torch.empty((n, 20), dtype=torch.float32, device=dev)
+    seed = inputs.CFG_BATCH["seed"]
+    _bbe.prefix_batch([(race, None, 0, 1, r.prefix_request, 0) for r, race in zip(reqs, races)],
+                      np.zeros(n, np.uint32), [r.target for r in reqs], seed, tick, pos, prev)
+    T, P, V = tick.cpu().numpy().view(np.uint32), pos.cpu().numpy(), prev.cpu().numpy()
+    specs = [(race, (int(T[i]), P[i, :r.n].copy(), V[i, :r.n].copy()), 0, r.n_sims, r.index, 0)
+             for i, (r, race) in enumerate(zip(reqs, races))]
+    wins = torch.zeros((n, 20), dtype=torch.int64, device=dev)
+    probs = torch.zeros((n, 20), dtype=torch.float64, device=dev)
+    stc = torch.zeros(1, dtype=torch.int64, device=dev)
+    t0 = time.perf_counter()
+    plan = _bbe.BatchPlan(specs, seed, wins, probs, stc, autotune=True)
+    setup_s = time.perf_counter() - t0
+    plan.launch()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    for a, b in evs:
+        a.record()
+        plan.launch()
+        b.record()
+    torch.cuda.synchronize()
+    ms = sorted(a.elapsed_time(b) for a, b in evs)
+    sims = sum(r.n_sims for r in reqs)
+    csteps = int(stc.item())
+    med = ms[len(ms) // 2] / 1e3
+    assert int(wins.sum().item()) == sims
+    return {"workload": "batch_inplay_4096: 4096 requests, n 5-20, remaining 5-100% of 2000, "
+                        "100-10^4 sims each, full finish order, one persistent graph launch",
+            "requests": n, "sims": sims, "competitor_steps": csteps,
+            "ms_per_launch": {"median": ms[len(ms) // 2], "min": ms[0]},
+            "sims_per_s": sims / med, "competitor_steps_per_s": csteps / med,
+            "alu_frac": csteps * ALGO_OPS_PER_COMPETITOR_STEP / med / VALU_PEAK_OPS,
+            "plan": plan.info(), "plan_setup_s": setup_s}
+
+
+def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int = 10_000):
+    """Queries per second: the surrogate (encode + forward on 10^4 queries)
+    against Monte-Carlo (10^4 simulations per query, winner only), on one
+    in-play state of the 20-competitor query race (dt = 0.1 s, 1000 ticks
+    in).  The network has its seeded initial weights: throughput does not
+    depend on training."""
+    import numpy as np
+    import torch
+
+    from paper_2108_02419_amd import _bbe, inputs
+    q = inputs.query_race()
+    comp, n = q["comp"], q["comp"].shape[0]
+    race = _bbe.Race(comp, inputs.TRACK_LEN)
+    dev = torch.device("cuda", 0)
+    tick = torch.empty(1, dtype=torch.int32, device=dev)
+    pos = torch.empty(n, dtype=torch.float32, device=dev)
+    prev = torch.empty(n, dtype=torch.float32, device=dev)
+    _bbe.race_advance(race, q["seed"], q["real_request"], 0, 1000, tick, pos, prev)
+    torch.cuda.synchronize()
+    state = (int(tick.item()), pos.cpu().numpy(), prev.cpu().numpy())
+    net = _bbe.Mlp(inputs.surrogate_init(), max_batch=8)
+    comp_b = torch.tensor(np.broadcast_to(np.pad(comp, ((0, 20 - n), (0, 0))),
+                                          (n_queries, 20, 5)).copy(), device=dev)
+    n_b = torch.full((n_queries,), n, dtype=torch.int32, device=dev)
+    pos_b = torch.zeros((n_queries, 20), dtype=torch.float32, device=dev)
+    prev_b = torch.zeros((n_queries, 20), dtype=torch.float32, device=dev)
+    pos_b[:, :n] = pos
+    prev_b[:, :n] = prev
+    x = torch.empty((n_queries, 160), dtype=torch.int16, device=dev)
+    sp = torch.empty((n_queries, 20), dtype=torch.float32, device=dev)
+    se = torch.empty(n_queries, dtype=torch.float32, device=dev)
+
+    def sur():
+        _bbe.encode_states(comp_b, n_b, pos_b, prev_b, inputs.TRACK_LEN, 0.1, x)
+        net.forward(x, n_b, sp, se)
+
+    for _ in range(3):
+        sur()
+    torch.cuda.synchronize()
+    reps = 20
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        sur()
+    b.record()
+    torch.cuda.synchronize()
+    sur_s = a.elapsed_time(b) / 1e3 / reps
+    specs = [(race, state, 0, mc_sims, i, 1) for i in range(mc_queries)]
+    wins = torch.zeros((mc_queries, 20), dtype=torch.int64, device=dev)
+    probs = torch.zeros((mc_queries, 20), dtype=torch.float64, device=dev)
+    plan = _bbe.BatchPlan(specs, q["seed"] + 1, wins, probs, None, autotune=True)
+    plan.launch()
+    torch.cuda.synchronize()
+    a.record()
+    for _ in range(3):
+        plan.launch()
+    b.record()
+    torch.cuda.synchronize()
+    mc_s = a.elapsed_time(b) / 1e3 / 3
+    sq, mq = n_queries / sur_s, mc_queries / mc_s
+    return {"workload": "query race n=20, dt 0.1 s, state at tick 1000; surrogate: 10^4 "
+                        "queries (encode + forward); MC: 100 queries x 10^4 sims, winner only",
+            "surrogate_queries_per_s": sq, "mc_queries_per_s": mq, "speedup": sq / mq,
+            "surrogate_ms_per_10k": sur_s * 1e3, "mc_ms_per_100": mc_s * 1e3}
 
 
 if __name__ == "__main__":
