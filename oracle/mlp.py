@@ -124,8 +124,10 @@ def encode(comp, n, pos, prev, track_len, dt):
     Slots hold the competitors by position, leader first (equal positions:
     lower index first), padded to 20.  Per slot 8 features, each one float32
     operation sequence: d/L, (L-d)/L, s/(7.5 dt), (lo+hi)/(15 dt) (the mean
-    free speed over 7.5), (hi-lo)/(hi+lo), rho/0.2, theta/2, and 1 (0 for
-    padding), with 7.5 dt and 15 dt rounded once to float32."""
+    free speed over 7.5), (hi-lo)/(hi+lo), rho/0.2, theta/2, and the
+    remaining distance over the mean free speed, feature 2 / feature 4 of
+    the rounded float32 values (0 for padding), with 7.5 dt and 15 dt
+    rounded once to float32."""
     f = np.float32
     comp = np.asarray(comp, np.float32)
     B = comp.shape[0]
@@ -140,7 +142,8 @@ def encode(comp, n, pos, prev, track_len, dt):
         for r, c in enumerate(order):
             lo, hi, _, rho, theta = comp[b, c]
             d, s = f(pos[b][c]), f(prev[b][c])
-            X[b, r] = [f(d / L), f(f(L - d) / L), f(s / c75), f(f(lo + hi) / c15),
-                       f(f(hi - lo) / f(hi + lo)), f(rho / f(0.2)), f(theta / f(2.0)), f(1.0)]
+            rem, spd = f(f(L - d) / L), f(f(lo + hi) / c15)
+            X[b, r] = [f(d / L), rem, f(s / c75), spd, f(f(hi - lo) / f(hi + lo)),
+                       f(rho / f(0.2)), f(theta / f(2.0)), f(rem / spd)]
             slot[b, r] = c
     return X.reshape(B, 160), slot

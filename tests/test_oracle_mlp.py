@@ -99,7 +99,9 @@ def test_encoding_by_hand_and_label_invariance():
     np.testing.assert_array_equal(f[0], np.array([0.75, 0.25, np.float32(0.6) / np.float32(0.75),
                                                   np.float32(14.0) / np.float32(1.5),
                                                   np.float32(2) / np.float32(14),
-                                                  np.float32(-0.2) / np.float32(0.2), 0.5, 1.0],
+                                                  np.float32(-0.2) / np.float32(0.2), 0.5,
+                                                  np.float32(0.25) / (np.float32(14.0) /
+                                                                      np.float32(1.5))],
                                                  np.float32))
     assert (f[3:] == 0).all()
     # relabelling the competitors permutes nothing in the encoding
