@@ -2,25 +2,30 @@
 // persistent launch (the paper's dry-run workload: many bettors each asking
 // for their own simulations of the race in play, Sections 3 and 6).
 //
-// batch_mc_kernel: a grid sized to the resident capacity of the GPU; every
-// wave repeatedly takes the next chunk index from a global atomic counter
-// (one atomic per chunk, issued by lane 0), runs that chunk's simulations
-// one generation of 64 at a time with the request's parameters in its LDS
-// records, and flushes the chunk's wins with one 64-bit atomic per
-// competitor.  Chunks are ordered on the host by competitor count and then
-// by expected length (longest first), so concurrently running waves mostly
-// share a code path and the shortest work ends the queue.
+// batch_mc_kernel<N>: one persistent launch per competitor count present in
+// the batch (each with the register budget of its own N), grid sized to the
+// resident capacity of the GPU; every wave repeatedly takes the next work
+// item of its group from a global atomic counter (one atomic per item,
+// issued by lane 0), runs that item's simulations one generation of 64 at a
+// time with the request's parameters in its LDS records, and flushes the
+// item's wins with one 64-bit atomic per competitor.  Within a group, items
+// are ordered by expected length, longest first, so the shortest work ends
+// the queue.
 #include "kernels.hpp"
 #include "race_sim.hpp"
+
+#include <utility>
 
 namespace bbe {
 
 // Per-wave LDS: draw table [kMaxN][64] floats, parameter records, win
-// histogram.
+// histogram, and the request's start state in slot order (positions,
+// previous steps, competitor ids) so that it does not occupy registers.
 constexpr uint32_t kWaveU = kMaxN * 256;
 constexpr uint32_t kWavePar = kMaxN * 32;
 constexpr uint32_t kWaveHist = 128;
-constexpr uint32_t kWaveBytes = kWaveU + kWavePar + kWaveHist;
+constexpr uint32_t kWaveInit = kMaxN * 12;
+constexpr uint32_t kWaveBytes = kWaveU + kWavePar + kWaveHist + kWaveInit;
 
 __device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v) {
 #pragma unroll
@@ -29,18 +34,30 @@ __device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v
 }
 
 template <int N>
-__device__ void run_chunk(const ReqDesc& rq, const Chunk& ch, char* smem, uint32_t wbase,
-                          int lane, uint32_t k0, uint32_t k1, unsigned long long* wins_row,
-                          unsigned long long& steps) {
+__device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, char* smem,
+                                          uint32_t wbase, int lane, uint32_t k0, uint32_t k1,
+                                          unsigned long long* wins_row,
+                                          unsigned long long& steps) {
     const uint32_t ucol = wbase + lane * 4;
     const uint32_t pbase = wbase + kWaveU;
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem + wbase + kWaveU + kWavePar);
+    float* d0 = reinterpret_cast<float*>(smem + wbase + kWaveU + kWavePar + kWaveHist);
+    float* s0 = d0 + kMaxN;
+    uint8_t* id0 = reinterpret_cast<uint8_t*>(s0 + kMaxN);
     write_params<N>(smem, pbase, rq.rc, lane);
-    if (lane < N) hist[lane] = 0u;
+    if (lane < N) {
+        hist[lane] = 0u;
+        d0[lane] = rq.d0[lane];
+        s0[lane] = rq.s0[lane];
+        id0[lane] = rq.id0[lane];
+    }
     for (uint32_t g = 0; g < ch.count; g += 64) {
         const bool live = g + lane < ch.count;
         const uint32_t sim = rq.sim_begin + ch.first + g + lane;
-        run_generation<N>(smem, ucol, pbase, rq.rc.L, rq.d0, rq.s0, rq.id0, rq.t0, live, sim,
+        // re-read the start state from LDS each generation rather than
+        // keeping 3N registers live across the loop
+        __asm__ volatile("" ::: "memory");
+        run_generation<N>(smem, ucol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim,
                           rq.request, k0, k1, rq.stop_after, nullptr, hist, steps);
     }
     if (lane < N) {
@@ -49,9 +66,19 @@ __device__ void run_chunk(const ReqDesc& rq, const Chunk& ch, char* smem, uint32
     }
 }
 
-template <int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) batch_mc_kernel(const BatchArgs a) {
-    __shared__ __attribute__((aligned(16))) char smem[WAVES * kWaveBytes];
+// Waves per SIMD the register allocation aims for: 4 where the body fits in
+// 128 VGPRs without spilling, else 3.
+template <int N>
+constexpr int batch_waves_per_eu() {
+    return (N == 16 || N >= 18) ? 3 : 4;
+}
+
+// Persistent kernel for the work items of one competitor count; up to 4
+// waves per workgroup (blockDim.x = 64 * waves).
+template <int N>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<N>())))
+    batch_mc_kernel(const BatchArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];  // waves * kWaveBytes
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint32_t wbase = wave * kWaveBytes;
@@ -62,21 +89,8 @@ __global__ void __launch_bounds__(64 * WAVES) batch_mc_kernel(const BatchArgs a)
         ci = __builtin_amdgcn_readfirstlane(ci);
         if (ci >= a.n_chunks) break;
         const Chunk ch = a.chunks[ci];
-        const ReqDesc& rq = a.reqs[ch.req];
-        unsigned long long* wrow = a.wins + (size_t)ch.req * kMaxN;
-        switch (ch.n) {
-#define BBE_CASE(n) \
-    case n:         \
-        run_chunk<n>(rq, ch, smem, wbase, lane, a.k0, a.k1, wrow, steps); \
-        break;
-            BBE_CASE(1) BBE_CASE(2) BBE_CASE(3) BBE_CASE(4) BBE_CASE(5)
-            BBE_CASE(6) BBE_CASE(7) BBE_CASE(8) BBE_CASE(9) BBE_CASE(10)
-            BBE_CASE(11) BBE_CASE(12) BBE_CASE(13) BBE_CASE(14) BBE_CASE(15)
-            BBE_CASE(16) BBE_CASE(17) BBE_CASE(18) BBE_CASE(19) BBE_CASE(20)
-#undef BBE_CASE
-            default:
-                break;
-        }
+        run_chunk<N>(a.reqs[ch.req], ch, smem, wbase, lane, a.k0, a.k1,
+                     a.wins + (size_t)ch.req * kMaxN, steps);
     }
     steps = wave_sum_u64b(steps);
     if (a.steps && lane == 0 && steps) atomicAdd(a.steps, steps);
@@ -194,31 +208,54 @@ __global__ void __launch_bounds__(64) prefix_batch_kernel(const ReqDesc* __restr
 
 // ---------------------------------------------------------------- launchers
 
-hipError_t launch_batch_mc(const BatchArgs& a, int waves_per_block, int grid, hipStream_t s) {
-    switch (waves_per_block) {
-        case 1: hipLaunchKernelGGL(batch_mc_kernel<1>, dim3(grid), dim3(64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(batch_mc_kernel<2>, dim3(grid), dim3(128), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(batch_mc_kernel<4>, dim3(grid), dim3(256), 0, s, a); break;
-        default: return hipErrorInvalidValue;
-    }
+template <int N>
+static hipError_t launch_batch_n(const BatchArgs& a, int waves_per_block, int grid,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(batch_mc_kernel<N>, dim3(grid), dim3(64 * waves_per_block),
+                       waves_per_block * kWaveBytes, s, a);
     return hipGetLastError();
 }
 
-int batch_blocks_per_cu(int waves_per_block) {
-    static int cache[5] = {0, 0, 0, 0, 0};
-    if (waves_per_block < 1 || waves_per_block > 4) return 1;
-    if (!cache[waves_per_block]) {
-        int nb = 0;
-        hipError_t e = hipErrorInvalidValue;
-        if (waves_per_block == 1)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<1>, 64, 0);
-        else if (waves_per_block == 2)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<2>, 128, 0);
-        else if (waves_per_block == 4)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<4>, 256, 0);
-        cache[waves_per_block] = (e == hipSuccess && nb > 0) ? nb : 1;
-    }
-    return cache[waves_per_block];
+template <int N>
+static int batch_occupancy_n(int waves_per_block) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<N>,
+                                                     64 * waves_per_block,
+                                                     waves_per_block * kWaveBytes) != hipSuccess)
+        nb = 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <int... I>
+static hipError_t dispatch_batch(int n, const BatchArgs& a, int w, int grid, hipStream_t s,
+                                 std::integer_sequence<int, I...>) {
+    using Fn = hipError_t (*)(const BatchArgs&, int, int, hipStream_t);
+    static constexpr Fn table[] = {launch_batch_n<I + 1>...};
+    return table[n - 1](a, w, grid, s);
+}
+
+template <int... I>
+static int dispatch_batch_occ(int n, int w, std::integer_sequence<int, I...>) {
+    using Fn = int (*)(int);
+    static constexpr Fn table[] = {batch_occupancy_n<I + 1>...};
+    return table[n - 1](w);
+}
+
+hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid,
+                           hipStream_t s) {
+    if (n < 1 || n > kMaxN || (waves_per_block != 1 && waves_per_block != 2 &&
+                               waves_per_block != 4))
+        return hipErrorInvalidValue;
+    return dispatch_batch(n, a, waves_per_block, grid, s,
+                          std::make_integer_sequence<int, kMaxN>{});
+}
+
+int batch_blocks_per_cu(int n, int waves_per_block) {
+    static int cache[kMaxN + 1][5] = {};
+    if (n < 1 || n > kMaxN || waves_per_block < 1 || waves_per_block > 4) return 1;
+    int& c = cache[n][waves_per_block];
+    if (!c) c = dispatch_batch_occ(n, waves_per_block, std::make_integer_sequence<int, kMaxN>{});
+    return c;
 }
 
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s) {

@@ -22,8 +22,15 @@ struct Shape {
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, Shape> g_tuned;
 
+struct Group {
+    int n;           // competitor count of every item in the group
+    uint32_t first;  // its items: chunks[first .. first + count)
+    uint32_t count;
+};
+
 struct Work {
     std::vector<bbe::Chunk> chunks;
+    std::vector<Group> groups;
 };
 
 // Expected ticks until the request's simulations end (used only to order
@@ -65,7 +72,13 @@ Work build_work(const std::vector<bbe::ReqDesc>& reqs, int sims_per_item) {
         return a.first > b.first;
     });
     w.chunks.reserve(items.size());
-    for (auto& it : items) w.chunks.push_back(it.second);
+    for (auto& it : items) {
+        const int n = (int)it.second.n;
+        if (w.groups.empty() || w.groups.back().n != n)
+            w.groups.push_back({n, (uint32_t)w.chunks.size(), 0u});
+        w.groups.back().count += 1;
+        w.chunks.push_back(it.second);
+    }
     return w;
 }
 
@@ -86,14 +99,15 @@ struct bbe_batch_plan {
     bbe::ReqDesc* d_reqs = nullptr;
     bbe::Chunk* d_chunks = nullptr;
     size_t chunk_cap = 0;
-    uint32_t* d_queue = nullptr;
+    uint32_t* d_queue = nullptr;  // one work-queue head per group
     uint32_t n_chunks = 0;
+    std::vector<Group> groups;
+    std::vector<int> grids;
     uint32_t k0 = 0, k1 = 0;
     unsigned long long* wins = nullptr;
     double* probs = nullptr;
     unsigned long long* steps = nullptr;
     Shape shape{4, 64};
-    int grid = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -106,17 +120,23 @@ hipError_t enqueue(bbe_batch_plan* p, hipStream_t s) {
     hipError_t e;
     if ((e = bbe::launch_zero_u64(p->wins, p->n_reqs * bbe::kMaxN, s)) != hipSuccess) return e;
     if (p->steps && (e = bbe::launch_zero_u64(p->steps, 1, s)) != hipSuccess) return e;
-    if ((e = bbe::launch_fill_u32(p->d_queue, 0u, 1, s)) != hipSuccess) return e;
-    bbe::BatchArgs a;
-    a.reqs = p->d_reqs;
-    a.chunks = p->d_chunks;
-    a.n_chunks = p->n_chunks;
-    a.queue = p->d_queue;
-    a.wins = p->wins;
-    a.steps = p->steps;
-    a.k0 = p->k0;
-    a.k1 = p->k1;
-    if ((e = bbe::launch_batch_mc(a, p->shape.waves_per_block, p->grid, s)) != hipSuccess) return e;
+    if ((e = bbe::launch_fill_u32(p->d_queue, 0u, (int)p->groups.size(), s)) != hipSuccess)
+        return e;
+    for (size_t g = 0; g < p->groups.size(); ++g) {
+        const Group& gr = p->groups[g];
+        bbe::BatchArgs a;
+        a.reqs = p->d_reqs;
+        a.chunks = p->d_chunks + gr.first;
+        a.n_chunks = gr.count;
+        a.queue = p->d_queue + g;
+        a.wins = p->wins;
+        a.steps = p->steps;
+        a.k0 = p->k0;
+        a.k1 = p->k1;
+        if ((e = bbe::launch_batch_mc(a, gr.n, p->shape.waves_per_block, p->grids[g], s)) !=
+            hipSuccess)
+            return e;
+    }
     if (p->probs &&
         (e = bbe::launch_batch_probs(p->wins, p->d_reqs, p->n_reqs, p->probs, s)) != hipSuccess)
         return e;
@@ -138,7 +158,15 @@ int upload_work(bbe_batch_plan* p, const Shape& sh) {
     if (e != hipSuccess) return hip_fail(e, "copying the work list");
     p->n_chunks = (uint32_t)w.chunks.size();
     p->shape = sh;
-    p->grid = bbe::batch_blocks_per_cu(sh.waves_per_block) * device_cus();
+    p->groups = w.groups;
+    p->grids.clear();
+    const int cus = device_cus();
+    for (const Group& g : w.groups) {
+        // resident capacity, but no more waves than the group has items
+        long cap = (long)bbe::batch_blocks_per_cu(g.n, sh.waves_per_block) * cus;
+        long need = ((long)g.count + sh.waves_per_block - 1) / sh.waves_per_block;
+        p->grids.push_back((int)std::max(1L, std::min(cap, need)));
+    }
     return BBE_OK;
 }
 
@@ -210,7 +238,7 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
 
     hipError_t e;
     if (hipMalloc(&p->d_reqs, sizeof(bbe::ReqDesc) * n_reqs) != hipSuccess ||
-        hipMalloc(&p->d_queue, sizeof(uint32_t)) != hipSuccess) {
+        hipMalloc(&p->d_queue, sizeof(uint32_t) * bbe::kMaxN) != hipSuccess) {
         destroy(p);
         return fail(BBE_ENOMEM, "device allocation of the request table failed");
     }
@@ -314,7 +342,11 @@ BBE_API int bbe_batch_plan_info(const bbe_batch_plan* plan, int* waves_per_block
                                 int* sims_per_item, int* n_items) {
     if (!plan) return fail(BBE_EINVAL, "plan is NULL");
     if (waves_per_block) *waves_per_block = plan->shape.waves_per_block;
-    if (grid) *grid = plan->grid;
+    if (grid) {
+        int g = 0;
+        for (int x : plan->grids) g = std::max(g, x);
+        *grid = g;
+    }
     if (sims_per_item) *sims_per_item = plan->shape.sims_per_item;
     if (n_items) *n_items = (int)plan->n_chunks;
     return ok();

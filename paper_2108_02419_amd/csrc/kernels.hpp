@@ -83,18 +83,21 @@ struct Chunk {
     uint32_t n;
 };
 
+// One launch serves the work items of one competitor count: chunks[0 ..
+// n_chunks) all have chunk.n == N of the kernel.
 struct BatchArgs {
     const ReqDesc* reqs;
     const Chunk* chunks;
     uint32_t n_chunks;
-    uint32_t* queue;            // work-queue head, zeroed before launch
+    uint32_t* queue;            // this group's work-queue head, zeroed before launch
     unsigned long long* wins;   // [n_reqs][kMaxN], zeroed before launch
     unsigned long long* steps;  // [1] or null, zeroed before launch
     uint32_t k0, k1;
 };
 
-hipError_t launch_batch_mc(const BatchArgs& a, int waves_per_block, int grid, hipStream_t s);
-int batch_blocks_per_cu(int waves_per_block);
+hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid,
+                           hipStream_t s);
+int batch_blocks_per_cu(int n, int waves_per_block);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
 hipError_t launch_batch_probs(const unsigned long long* wins, const ReqDesc* reqs, int n_reqs,
                               double* probs, hipStream_t s);

@@ -34,8 +34,16 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
+// Waves per SIMD the register allocation aims for: 4 where the body fits in
+// 128 VGPRs without spilling, else 3.
 template <int N>
-__global__ void __launch_bounds__(kBlock) race_mc_kernel(const SimArgs a) {
+constexpr int mc_waves_per_eu() {
+    return (N == 18 || N == 19) ? 3 : 4;
+}
+
+template <int N>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<N>()))) race_mc_kernel(const SimArgs a) {
     using Lay = BlockLds<N>;
     __shared__ __attribute__((aligned(1024))) char smem[Lay::kBytes];
     const int wave = threadIdx.x >> 6;

@@ -94,54 +94,58 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
         if (4 * b + 3 < N) lds_st_f32(smem, ucol + (4 * b + 3) * 256, unit24(w.w));
     }
 
-    // 2. competitor ahead.  Slots are in (position, index) order, so with
-    //    distinct positions it is the next slot; where positions are equal
-    //    it is the first slot of the next higher position, found by a pass
-    //    from the top (that slot is the lowest index of its group).
-    float ahead_d[N], s_ahead[N];
-    bool tie = false;
+    // 2.-4. Slots from the top down.  Slots are in (position, index) order,
+    //    so the competitor ahead of slot k is the first slot above it with a
+    //    larger position: slot k+1, or -- where positions are equal -- the
+    //    one found for slot k+1, carried down in (nd, ns).  The start-of-tick
+    //    position and step of slot k+1 are kept in (d_up, s_up) because the
+    //    update overwrites the slot (synchronous update).  Each slot's draw
+    //    and parameter record are read from LDS kPf slots ahead of use.
+    constexpr int kPf = 4;
+    float pu[N], pth[N];
+    float4 pp[N];
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) {
-        ahead_d[k] = sl.d[k + 1];
-        s_ahead[k] = sl.s[k + 1];
-        tie |= (sl.d[k + 1] == sl.d[k]) && (sl.d[k] < L);
+    for (int k = N - 1; k >= 0 && k >= N - kPf; --k) {
+        const uint32_t id = sl.id[k];
+        pu[k] = lds_f32(smem, ucol + (id << 8));
+        pp[k] = *reinterpret_cast<const float4*>(smem + pbase + (id << 5));
+        pth[k] = lds_f32(smem, pbase + (id << 5) + 16);
     }
-    ahead_d[N - 1] = __builtin_inff();
-    s_ahead[N - 1] = 0.0f;
-    if (tie) {
-        float nd = __builtin_inff(), ns = 0.0f;  // nearest above the slot just visited
-#pragma unroll
-        for (int k = N - 2; k >= 0; --k) {
-            bool gt = sl.d[k + 1] > sl.d[k];
-            nd = gt ? sl.d[k + 1] : nd;
-            ns = gt ? sl.s[k + 1] : ns;
-            ahead_d[k] = nd;
-            s_ahead[k] = ns;
-        }
-    }
-
-    // 3. Eq. 1 and 4. synchronous update
+    float nd = __builtin_inff(), ns = 0.0f;
+    float d_up = __builtin_inff(), s_up = 0.0f;
     uint32_t cross = 0;
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-        const uint32_t id = sl.id[k];
-        const float u = lds_f32(smem, ucol + (id << 8));
-        const uint32_t po = pbase + (id << 5);
-        const float4 p = *reinterpret_cast<const float4*>(smem + po);
-        const float theta = lds_f32(smem, po + 16);
+    for (int k = N - 1; k >= 0; --k) {
+        if (k - kPf >= 0) {
+            const uint32_t id = sl.id[k - kPf];
+            pu[k - kPf] = lds_f32(smem, ucol + (id << 8));
+            pp[k - kPf] = *reinterpret_cast<const float4*>(smem + pbase + (id << 5));
+            pth[k - kPf] = lds_f32(smem, pbase + (id << 5) + 16);
+        }
         const float d = sl.d[k];
+        const float s = sl.s[k];
+        const bool gt = d_up > d;
+        nd = gt ? d_up : nd;
+        ns = gt ? s_up : ns;
+        // Eq. 1
+        const float4 p = pp[k];
         float R = p.z + p.w * d;
-        float x = p.x + p.y * u;
+        float x = p.x + p.y * pu[k];
         float s_free = R * x;
-        float s_blocked = R * fminf(sl.s[k], s_ahead[k]);
-        float gap = ahead_d[k] - d;  // +inf when nobody is ahead
-        float S = (gap <= theta) ? s_blocked : s_free;
+        // min of two positive steps (ns = 0 only when nobody is ahead)
+        float s_min = __uint_as_float(min(__float_as_uint(s), __float_as_uint(ns)));
+        float s_blocked = R * s_min;
+        float gap = nd - d;  // +inf when nobody is ahead
+        float S = (gap <= pth[k]) ? s_blocked : s_free;
+        // synchronous update
         bool run = d < L;
         float dn = d + S;
         bool cr = run && (dn >= L);
         cross |= cr ? (1u << k) : 0u;
         sl.d[k] = (run && !cr) ? dn : d;
-        sl.s[k] = run ? S : sl.s[k];
+        sl.s[k] = run ? S : s;
+        d_up = d;
+        s_up = s;
     }
     return cross;
 }
