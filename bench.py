@@ -239,8 +239,8 @@ def batch_leg(steps: int):
 def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int = 10_000):
     """Queries per second: the surrogate (encode + forward on 10^4 queries)
     against Monte-Carlo (10^4 simulations per query, winner only), on one
-    in-play state of the 20-competitor query race (dt = 0.1 s, 1000 ticks
-    in).  The network has its seeded initial weights: throughput does not
+    in-play state of the 20-competitor query race (dt = 1 s, 100 ticks
+    in, about a third of the race).  The network has its seeded initial weights: throughput does not
     depend on training."""
     import numpy as np
     import torch
@@ -253,7 +253,7 @@ def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int =
     tick = torch.empty(1, dtype=torch.int32, device=dev)
     pos = torch.empty(n, dtype=torch.float32, device=dev)
     prev = torch.empty(n, dtype=torch.float32, device=dev)
-    _bbe.race_advance(race, q["seed"], q["real_request"], 0, 1000, tick, pos, prev)
+    _bbe.race_advance(race, q["seed"], q["real_request"], 0, 100, tick, pos, prev)
     torch.cuda.synchronize()
     state = (int(tick.item()), pos.cpu().numpy(), prev.cpu().numpy())
     net = _bbe.Mlp(inputs.surrogate_init(), max_batch=8)
@@ -269,7 +269,8 @@ def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int =
     se = torch.empty(n_queries, dtype=torch.float32, device=dev)
 
     def sur():
-        _bbe.encode_states(comp_b, n_b, pos_b, prev_b, inputs.TRACK_LEN, 0.1, x)
+        _bbe.encode_states(comp_b, n_b, pos_b, prev_b, inputs.TRACK_LEN,
+                           inputs.CFG_QUERY["dt"], x)
         net.forward(x, n_b, sp, se)
 
     for _ in range(3):
@@ -296,7 +297,7 @@ def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int =
     torch.cuda.synchronize()
     mc_s = a.elapsed_time(b) / 1e3 / 3
     sq, mq = n_queries / sur_s, mc_queries / mc_s
-    return {"workload": "query race n=20, dt 0.1 s, state at tick 1000; surrogate: 10^4 "
+    return {"workload": "query race n=20, dt 1 s, state at tick 100; surrogate: 10^4 "
                         "queries (encode + forward); MC: 100 queries x 10^4 sims, winner only",
             "surrogate_queries_per_s": sq, "mc_queries_per_s": mq, "speedup": sq / mq,
             "surrogate_ms_per_10k": sur_s * 1e3, "mc_ms_per_100": mc_s * 1e3}

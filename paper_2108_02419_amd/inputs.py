@@ -36,10 +36,10 @@ CFG_START_N20 = dict(name="mc_start_n20_1e6", n=20, dt=1.0, param_seed=2, mc_see
                      n_sims=1_000_000, stop_after=None)
 CFG_BATCH = dict(name="batch_inplay_4096", n_requests=4096, dt=1.0, seed=3, n_lo=5, n_hi=20,
                  frac_lo=0.05, frac_hi=1.0, sims_lo=100, sims_hi=10_000)
-CFG_SURROGATE = dict(name="surrogate_train", dt=0.1, seed=4, n_lo=5, n_hi=20, p_n20=0.25,
+CFG_SURROGATE = dict(name="surrogate_train", dt=1.0, seed=4, n_lo=5, n_hi=20, p_n20=0.25,
                      frac_lo=0.05, frac_hi=1.0, label_sims=10_000)
-CFG_QUERY = dict(name="inplay_query_loop", n=20, dt=0.1, seed=5, real_request=0xC0000000,
-                 n_bettors=10_000, every=10, audit_frac=0.01, mc_sims=10_000, judge_sims=1_000_000)
+CFG_QUERY = dict(name="inplay_query_loop", n=20, dt=1.0, seed=5, real_request=0xC0000000,
+                 n_bettors=10_000, every=1, audit_frac=0.01, mc_sims=10_000, judge_sims=1_000_000)
 
 PREFIX_REQUEST_BIT = 0x80000000  # request ids used for the runs that produce in-play states
 
@@ -109,7 +109,8 @@ def batch_requests(cfg: dict = CFG_BATCH, n_requests: int | None = None) -> list
 
 def surrogate_states(n_states: int, cfg: dict = CFG_SURROGATE, first: int = 0) -> list[RequestSpec]:
     """Training / evaluation states for the surrogate: like the batched
-    requests but at dt = 0.1 s, with a quarter of the races at n = 20."""
+    requests (dt = 1 s, the paper's timing step), with a quarter of the
+    races at n = 20."""
     out = []
     for r in range(first, first + n_states):
         rng = np.random.default_rng([cfg["seed"], r])

@@ -35,7 +35,7 @@ def _plan_probs(specs, seed, n_rows):
     return plan, probs
 
 
-def run(params, every=10, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
+def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
         judge_sims=1_000_000, entropy_frac=0.95, max_rounds=None, log=print):
     cfg = inputs.CFG_QUERY
     q = inputs.query_race(cfg)
@@ -141,7 +141,7 @@ def run(params, every=10, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
 def main():
     ap = argparse.ArgumentParser(description="in-play query loop")
     ap.add_argument("--params", required=True, help="trained surrogate parameters (.npy)")
-    ap.add_argument("--every", type=int, default=10)
+    ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--bettors", type=int, default=10_000)
     ap.add_argument("--judge-sims", type=int, default=1_000_000)
     ap.add_argument("--max-rounds", type=int, default=None)

@@ -197,21 +197,27 @@ def main():
         f"({steps / label_s:.3e} competitor-steps/s)")
     x, n, _, target = encode(ds, probs)
     net = _bbe.Mlp(inputs.surrogate_init(args.seed), max_batch=args.batch)
+    t1 = time.perf_counter()
     hist = train(net, x, n, target, args.epochs, args.batch, args.lr, log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
 
     # held-out states judged by high-sample Monte-Carlo
     espec = inputs.surrogate_states(args.eval_states, first=10_000_000)
     eds = gen_states(espec, args.seed + 1)
     jprobs, jsteps = mc_probs(eds, args.judge_sims, args.seed + 1, request_base=1 << 24)
-    mprobs, _ = mc_probs(eds, 10_000, args.seed + 2, request_base=1 << 25)
     ex, en, _, jt = encode(eds, jprobs)
-    _, _, _, mt = encode(eds, mprobs)
     pred, ent = predict(net, ex, en)
+    rp = {}
+    for d in (4, 16, 64, 10_000):  # RP(d) bettors: d simulations each
+        dprobs, _ = mc_probs(eds, d, args.seed + 2, request_base=(1 << 25) + d)
+        rp[f"rp{d}_vs_judge"] = errors(encode(eds, dprobs)[3], jt, en)
     torch.cuda.synchronize()
     res = dict(train_states=len(ds), label_sims=args.label_sims, epochs=args.epochs,
+               batch=args.batch, lr=args.lr, train_seconds=train_s,
                label_seconds=label_s, label_competitor_steps=steps, loss_history=hist,
                eval_states=len(eds), judge_sims=args.judge_sims,
-               surrogate_vs_judge=errors(pred, jt, en), mc1e4_vs_judge=errors(mt, jt, en))
+               surrogate_vs_judge=errors(pred, jt, en), **rp)
     log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
     np.save(os.path.join(args.out, "params.npy"), net.params())
     with open(os.path.join(args.out, "result.json"), "w") as f:
