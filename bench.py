@@ -9,9 +9,12 @@ seeded and synthetic (paper_2108_02419_amd/inputs.py); every step uses a
 new Monte-Carlo seed.
 
 Prints ONE JSON line.  `value` is simulations per second; the roofline
-object prices the Monte-Carlo kernel against the vector-ALU peak of the chip
-(256 CUs x 4 SIMDs x 32 lanes x 2.4 GHz lane-operations per second) using the
-algorithmic cost per competitor-step; the cpu_baseline object times the
+object prices the Monte-Carlo kernel against the vector-ALU issue peak of
+the chip (256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz: a wave64 vector
+instruction occupies its SIMD for four cycles) using the algorithmic
+instruction count per competitor-step, and takes the HBM traffic per launch
+from the committed counter profile when that profile was taken on the
+current kernel sources; the cpu_baseline object times the
 CPU oracle on a bounded sample of the same workload.  Two more objects
 measure the other workloads of the path: `batch` (4096 uneven in-play
 requests in one graph-captured persistent launch) and `surrogate` (queries
@@ -30,12 +33,52 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Algorithmic vector work per competitor-step, in 32-bit lane-operation
-# equivalents (a 32x32->64 product counted 3): a quarter of one
-# Philox4x32-10 block plus its conversion (28), the competitor-ahead query
-# with a maintained order (3), Eq. 1 (9), the update and finish test (4).
-ALGO_OPS_PER_COMPETITOR_STEP = 44.0
-VALU_PEAK_OPS = 256 * 4 * 32 * 2.4e9  # lane-ops/s: CUs x SIMDs x lanes x clock
+# Algorithmic vector work per competitor-step, in wave64 vector-instruction
+# issue slots (each 32x32->64 product is one v_mad_u64_u32, each three-way
+# xor one v_bitop3_b32): a quarter of one Philox4x32-10 block (10 products,
+# 10 xors over the block's 4 words: 5 + 5) and the draw's conversion (2),
+# Eq. 1 (R 2, free step 2, min 1, product 1, gap 1, test 1, select 1 = 9),
+# the update and finish test (3), and the competitor-ahead query with a
+# maintained order (carry past equal positions 3, one order check 1).
+ALGO_OPS_PER_COMPETITOR_STEP = 28.0
+VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9  # lane-instr/s: CUs x SIMDs x lanes/clock x clock
+
+# The counter profile of the Monte-Carlo kernel on this workload, and the
+# sources it was taken on.
+PROFILE = os.path.join(ROOT, "profiles", "race_mc_kernel_n20_1e6.md")
+KERNEL_SOURCES = ["race_kernels.hip", "race_sim.hpp", "race_common.hpp", "kernels.hpp"]
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2108_02419_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def profiled_traffic():
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy-probe
+    factors) from the committed profile, or None if the profile is missing or
+    was taken on other kernel sources."""
+    try:
+        with open(PROFILE) as f:
+            text = f.read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip().strip("`")
+        for key in ("kernel_sources_sha256:", "traffic_bytes_per_launch:"):
+            if line.startswith(key):
+                vals[key] = line[len(key):].strip()
+    if vals.get("kernel_sources_sha256:") != kernel_sources_sha256():
+        return None
+    try:
+        return float(vals["traffic_bytes_per_launch:"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(c, target_s: float = 12.0):
@@ -174,8 +217,9 @@ def main() -> int:
         "device": {"name": torch.cuda.get_device_name(0),
                    "cus": torch.cuda.get_device_properties(0).multi_processor_count},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
-                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS, "traffic": None,
-                     "ops_per_competitor_step": ALGO_OPS_PER_COMPETITOR_STEP},
+                     "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
+                     "traffic": profiled_traffic(),
+                     "instr_per_competitor_step": ALGO_OPS_PER_COMPETITOR_STEP},
     }
     if not args.no_batch:
         line["batch"] = batch_leg(args.batch_steps)

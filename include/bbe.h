@@ -76,7 +76,10 @@ typedef struct bbe_state {
  * track of length track_len (finite, > 0).  `comp` is a host array of n
  * competitors, copied (the caller may free it on return).  Also rejects
  * races whose slowest possible free step, lo*pref*(1-|rho|), would need
- * more than BBE_EXPECTED_TICK_BOUND ticks to cover the track.
+ * more than BBE_EXPECTED_TICK_BOUND ticks to cover the track, and
+ * competitors whose scaled span pref*(hi-lo) (float32) is neither 0 nor at
+ * least 2^-102 (the kernels apply the 2^-24 of the draw to the span, which
+ * is exact only there; any sensible race is far inside).
  * Errors: BBE_EINVAL, BBE_ENOMEM.                                          */
 int bbe_race_init(const bbe_competitor *comp, int n, float track_len, bbe_race **out);
 

@@ -70,7 +70,7 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
 // 128 VGPRs without spilling, else 3.
 template <int N>
 constexpr int batch_waves_per_eu() {
-    return (N == 16 || N >= 18) ? 3 : 4;
+    return 4;
 }
 
 // Persistent kernel for the work items of one competitor count; up to 4
@@ -130,11 +130,11 @@ __device__ void run_prefix_lane(const ReqDesc& rq, char* smem, uint32_t ucol, ui
                                 float* pos_out, float* prev_out) {
     for (int c = 0; c < N; ++c) {
         float4* rec = reinterpret_cast<float4*>(smem + pbase + c * 32);
-        rec[0] = make_float4(rq.rc.elo[c], rq.rc.espan[c], rq.rc.alpha[c], rq.rc.beta[c]);
+        rec[0] = make_float4(rq.rc.elo[c], rq.rc.espan24[c], rq.rc.alpha[c], rq.rc.beta[c]);
         rec[1] = make_float4(rq.rc.theta[c], 0.0f, 0.0f, 0.0f);
     }
     Slots<N> sl;
-    slots_reset<N>(sl, rq.d0, rq.s0, rq.id0);
+    slots_reset<N>(sl, rq.d0, rq.s0, rq.id0, pbase);
     uint32_t t = rq.t0;
     bool ok = true;
     for (;;) {
@@ -150,31 +150,14 @@ __device__ void run_prefix_lane(const ReqDesc& rq, char* smem, uint32_t ucol, ui
             ok = false;
             break;
         }
-        // this lane alone: passes until sorted
-        for (int pass = 0; pass < N; ++pass) {
-            bool sw = false;
-#pragma unroll
-            for (int k = 0; k < N - 1; ++k) {
-                if (slot_key(sl.d[k], sl.id[k]) > slot_key(sl.d[k + 1], sl.id[k + 1])) {
-                    float td = sl.d[k]; sl.d[k] = sl.d[k + 1]; sl.d[k + 1] = td;
-                    float ts = sl.s[k]; sl.s[k] = sl.s[k + 1]; sl.s[k + 1] = ts;
-                    uint32_t ti = sl.id[k]; sl.id[k] = sl.id[k + 1]; sl.id[k + 1] = ti;
-                    sw = true;
-                }
-            }
-            if (!sw) break;
-        }
+        slots_restore<N>(sl);
     }
     *tick_out = ok ? t : 0xFFFFFFFFu;
     for (int c = 0; c < kMaxN; ++c) {
         pos_out[c] = 0.0f;
         prev_out[c] = 0.0f;
     }
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        pos_out[sl.id[k]] = sl.d[k];
-        prev_out[sl.id[k]] = sl.s[k];
-    }
+    slots_store<N>(sl, pbase, pos_out, prev_out);
 }
 
 __global__ void __launch_bounds__(64) prefix_batch_kernel(const ReqDesc* __restrict__ reqs,

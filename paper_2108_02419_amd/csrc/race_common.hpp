@@ -19,11 +19,15 @@ constexpr uint32_t kTickLimit = 1u << 20;
 //   elo = fl(P*lo), espan = fl(P*fl(hi - lo))   free step = elo + espan*u
 //   alpha = fl(1 - rho), beta = fl(fl(2*rho)/L) R_c(d) = alpha + beta*d
 //   theta                                        blocked iff gap <= theta
+// The kernels take the draw as the integer k = w >> 8 (u = k * 2^-24) and
+// the span pre-scaled, espan24 = espan * 2^-24: a power-of-two scaling, exact
+// whenever espan is 0 or at least 2^-102 (the host rejects other spans), so
+// fl(espan24 * k) = fl(espan * u) bit for bit.
 struct RaceConst {
     float L;
     int n;
     float elo[kMaxN];
-    float espan[kMaxN];
+    float espan24[kMaxN];
     float alpha[kMaxN];
     float beta[kMaxN];
     float theta[kMaxN];
@@ -32,11 +36,16 @@ struct RaceConst {
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round forms the
 // 64-bit products of the two even counter words with the round multipliers
 // (one v_mad_u64_u32 each); the high halves are xored with the odd words
-// and the round key, the low halves become the new odd words, and the key
-// advances by the Weyl increments.
+// and the round key (one three-input v_bitop3_b32 each once all three
+// operands vary per lane), the low halves
+// become the new odd words, and the key advances by the Weyl increments.
 struct U4 {
     uint32_t x, y, z, w;
 };
+
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // truth table of a ^ b ^ c
+}
 
 __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                             uint32_t k0, uint32_t k1) {
@@ -44,8 +53,18 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     for (int r = 0; r < 10; ++r) {
         uint64_t p0 = (uint64_t)c0 * 0xD2511F53u;
         uint64_t p1 = (uint64_t)c2 * 0xCD9E8D57u;
-        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        // In the race kernels the counter words t, request and block are
+        // wave-uniform and only `sim` varies per lane, so the first rounds
+        // mix at most one lane-varying word into each xor: plain xors let
+        // the compiler keep the uniform parts on the scalar unit there.
+        uint32_t n0, n2;
+        if (r < 3) {
+            n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+            n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        } else {
+            n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+            n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        }
         c0 = n0;
         c1 = (uint32_t)p1;
         c2 = n2;
@@ -56,9 +75,10 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
-// 24-bit uniform in [0, 1 - 2^-24], exact in float32.
-__device__ __forceinline__ float unit24(uint32_t w) {
-    return (float)(w >> 8) * 0x1p-24f;
+// The draw as the integer k = w >> 8 in [0, 2^24), exact in float32; the
+// uniform of the model is u = k * 2^-24.
+__device__ __forceinline__ float draw24(uint32_t w) {
+    return (float)(w >> 8);
 }
 
 }  // namespace bbe

@@ -38,7 +38,7 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 // 128 VGPRs without spilling, else 3.
 template <int N>
 constexpr int mc_waves_per_eu() {
-    return (N == 18 || N == 19) ? 3 : 4;
+    return 4;
 }
 
 template <int N>
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(64) race_prefix_kernel(const PrefixArgs a) {
     __syncthreads();
     if (lane != 0) return;
     Slots<N> sl;
-    slots_reset<N>(sl, a.d0, a.s0, a.id0);
+    slots_reset<N>(sl, a.d0, a.s0, a.id0, kPar);
     uint32_t t = a.t0;
     bool ok = true;
     for (;;) {
@@ -113,11 +113,7 @@ __global__ void __launch_bounds__(64) race_prefix_kernel(const PrefixArgs a) {
         slots_restore<N>(sl);
     }
     *a.tick_out = ok ? t : 0xFFFFFFFFu;
-#pragma unroll
-    for (int k = 0; k < N; ++k) {
-        a.pos_out[sl.id[k]] = sl.d[k];
-        a.prev_out[sl.id[k]] = sl.s[k];
-    }
+    slots_store<N>(sl, kPar, a.pos_out, a.prev_out);
 }
 
 __global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int n) {

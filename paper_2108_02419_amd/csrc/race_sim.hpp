@@ -2,21 +2,23 @@
 // (paper Section 3, Eq. 1).
 //
 // Layout.  A lane keeps its competitors in N register "slots" sorted by
-// position (ascending; finished competitors are parked at +inf at the
-// top).  Slot k holds the position d[k], the previous step s[k] and the
-// index id[k] of the competitor that occupies it, which locates its draw
-// and its parameter record in LDS.  Slots are kept in
-// (position, competitor index) order, so the competitor ahead of slot k is
-// the first slot above it with a larger position -- slot k+1 unless
-// positions are equal -- and the query of Eq. 1 costs O(1) per competitor
-// instead of a scan over all pairs.
+// position (ascending; finished competitors are parked at the top with a
+// NaN position).  Slot k holds the position d[k], the LDS byte offset
+// rec[k] of its competitor's parameter record (pbase + 32 * competitor
+// index; it also locates the competitor's draw) and the previous step s[k].
+// Slots are ordered by the 64-bit key (bits(d) << 32) | rec: non-negative
+// floats, +inf and the parking NaN order like their bit patterns, and rec
+// grows with the competitor index, so this is (position, index) order.  The
+// competitor ahead of slot k is then the first slot above it with a larger
+// position -- slot k+1 unless positions are equal -- and the query of Eq. 1
+// costs O(1) per competitor instead of a scan over all pairs.
 //
 // One tick (all 64 lanes at the same absolute tick t):
 //   1. draws in competitor order: Philox4x32-10(key = seed,
 //      ctr = (t, sim, request, b)) for blocks b = 0 .. ceil(N/4)-1;
-//      competitor c takes word c&3 of block c>>2, u = (w >> 8) * 2^-24; the
-//      draws go to the lane's column of an LDS table and each slot reads
-//      the draw of its own competitor;
+//      competitor c takes word c&3 of block c>>2, as the integer
+//      k = w >> 8 (u = k * 2^-24); the draws go to the lane's column of an
+//      LDS table and each slot reads the draw of its own competitor;
 //   2. competitor ahead: the running competitor with the smallest position
 //      greater than d_c (lowest index among equal positions); gap =
 //      fl(d_ahead - d_c), +inf if nobody is ahead;
@@ -26,8 +28,10 @@
 //      competitor whose new position reaches L crosses the line;
 //   5. this tick's finishers are ranked after the earlier ones, among
 //      themselves by the fraction fl((L - d_old)/S), then by index, and are
-//      parked at +inf;
-//   6. bubble passes restore the slot order.
+//      parked (position NaN: every comparison with it is false, so a parked
+//      slot never crosses again and is never "ahead" of anyone);
+//   6. compare-exchange passes, alternately upward and downward, restore the
+//      slot order.
 #pragma once
 
 #include "race_common.hpp"
@@ -37,9 +41,14 @@ namespace bbe {
 template <int N>
 struct Slots {
     float d[N];
+    uint32_t rec[N];
     float s[N];
-    uint32_t id[N];
 };
+
+// Order key of a slot.
+__device__ __forceinline__ uint64_t slot_key(float d, uint32_t rec) {
+    return ((uint64_t)__float_as_uint(d) << 32) | rec;
+}
 
 __device__ __forceinline__ float lds_f32(const char* smem, uint32_t off) {
     return *reinterpret_cast<const float*>(smem + off);
@@ -49,36 +58,43 @@ __device__ __forceinline__ void lds_st_f32(char* smem, uint32_t off, float v) {
     *reinterpret_cast<float*>(smem + off) = v;
 }
 
-// Writes the parameter records of a race into a wave's record block:
-// record c = (elo, espan, alpha, beta, theta, -, -, -) at pbase + 32*c.
+// The parking position of finished competitors (a quiet NaN whose bit
+// pattern exceeds that of +inf).
+__device__ __forceinline__ float parked() {
+    return __uint_as_float(0x7FC00000u);
+}
+
+// Writes the parameter records of a race into a record block: record c =
+// (elo, espan24, alpha, beta, theta, -, -, -) at pbase + 32*c.
 template <int N>
 __device__ __forceinline__ void write_params(char* smem, uint32_t pbase, const RaceConst& rc,
                                             int lane) {
     if (lane < N) {
         float4* rec = reinterpret_cast<float4*>(smem + pbase + lane * 32);
-        rec[0] = make_float4(rc.elo[lane], rc.espan[lane], rc.alpha[lane], rc.beta[lane]);
+        rec[0] = make_float4(rc.elo[lane], rc.espan24[lane], rc.alpha[lane], rc.beta[lane]);
         rec[1] = make_float4(rc.theta[lane], 0.0f, 0.0f, 0.0f);
     }
 }
 
 // Loads an initial state already in slot order (positions ascending, equal
-// positions by competitor index).
+// positions by competitor index); `pbase` locates the parameter records.
 template <int N>
 __device__ __forceinline__ void slots_reset(Slots<N>& sl, const float* __restrict__ d0,
                                             const float* __restrict__ s0,
-                                            const uint8_t* __restrict__ id0) {
+                                            const uint8_t* __restrict__ id0, uint32_t pbase) {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
         sl.d[k] = d0[k];
+        sl.rec[k] = pbase + 32u * id0[k];
         sl.s[k] = s0[k];
-        sl.id[k] = id0[k];
     }
 }
 
 // Steps 1-4 for one lane.  `ucol` is the byte offset of this lane's column
 // of the draw table (competitor c's draw at ucol + 256*c), `pbase` that of
-// the wave's parameter records.  Returns the bit mask of slots that crossed
-// the line (their d[] still holds the start-of-tick position).
+// the parameter records.  Returns the bit mask of slots that crossed the
+// line (their position still holds the start-of-tick value; their s holds
+// the step S that took them over).
 template <int N>
 __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_t ucol,
                                                uint32_t pbase, float L, uint32_t t,
@@ -88,10 +104,10 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
 #pragma unroll
     for (int b = 0; b < (N + 3) / 4; ++b) {
         U4 w = philox4x32_10(t, sim, request, (uint32_t)b, k0, k1);
-        if (4 * b + 0 < N) lds_st_f32(smem, ucol + (4 * b + 0) * 256, unit24(w.x));
-        if (4 * b + 1 < N) lds_st_f32(smem, ucol + (4 * b + 1) * 256, unit24(w.y));
-        if (4 * b + 2 < N) lds_st_f32(smem, ucol + (4 * b + 2) * 256, unit24(w.z));
-        if (4 * b + 3 < N) lds_st_f32(smem, ucol + (4 * b + 3) * 256, unit24(w.w));
+        if (4 * b + 0 < N) lds_st_f32(smem, ucol + (4 * b + 0) * 256, draw24(w.x));
+        if (4 * b + 1 < N) lds_st_f32(smem, ucol + (4 * b + 1) * 256, draw24(w.y));
+        if (4 * b + 2 < N) lds_st_f32(smem, ucol + (4 * b + 2) * 256, draw24(w.z));
+        if (4 * b + 3 < N) lds_st_f32(smem, ucol + (4 * b + 3) * 256, draw24(w.w));
     }
 
     // 2.-4. Slots from the top down.  Slots are in (position, index) order,
@@ -99,17 +115,19 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
     //    larger position: slot k+1, or -- where positions are equal -- the
     //    one found for slot k+1, carried down in (nd, ns).  The start-of-tick
     //    position and step of slot k+1 are kept in (d_up, s_up) because the
-    //    update overwrites the slot (synchronous update).  Each slot's draw
+    //    update overwrites the slot (synchronous update).  The draw of
+    //    competitor c sits at ucol + 256*c = ubias + 8*rec; each slot's draw
     //    and parameter record are read from LDS kPf slots ahead of use.
+    const uint32_t ubias = ucol - 8u * pbase;
     constexpr int kPf = 4;
     float pu[N], pth[N];
     float4 pp[N];
 #pragma unroll
     for (int k = N - 1; k >= 0 && k >= N - kPf; --k) {
-        const uint32_t id = sl.id[k];
-        pu[k] = lds_f32(smem, ucol + (id << 8));
-        pp[k] = *reinterpret_cast<const float4*>(smem + pbase + (id << 5));
-        pth[k] = lds_f32(smem, pbase + (id << 5) + 16);
+        const uint32_t rec = sl.rec[k];
+        pu[k] = lds_f32(smem, ubias + (rec << 3));
+        pp[k] = *reinterpret_cast<const float4*>(smem + rec);
+        pth[k] = lds_f32(smem, rec + 16);
     }
     float nd = __builtin_inff(), ns = 0.0f;
     float d_up = __builtin_inff(), s_up = 0.0f;
@@ -117,126 +135,151 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
 #pragma unroll
     for (int k = N - 1; k >= 0; --k) {
         if (k - kPf >= 0) {
-            const uint32_t id = sl.id[k - kPf];
-            pu[k - kPf] = lds_f32(smem, ucol + (id << 8));
-            pp[k - kPf] = *reinterpret_cast<const float4*>(smem + pbase + (id << 5));
-            pth[k - kPf] = lds_f32(smem, pbase + (id << 5) + 16);
+            const uint32_t rec = sl.rec[k - kPf];
+            pu[k - kPf] = lds_f32(smem, ubias + (rec << 3));
+            pp[k - kPf] = *reinterpret_cast<const float4*>(smem + rec);
+            pth[k - kPf] = lds_f32(smem, rec + 16);
         }
         const float d = sl.d[k];
         const float s = sl.s[k];
-        const bool gt = d_up > d;
+        const bool gt = d_up > d;  // false next to a parked (NaN) slot
         nd = gt ? d_up : nd;
         ns = gt ? s_up : ns;
         // Eq. 1
         const float4 p = pp[k];
         float R = p.z + p.w * d;
         float x = p.x + p.y * pu[k];
-        float s_free = R * x;
         // min of two positive steps (ns = 0 only when nobody is ahead)
         float s_min = __uint_as_float(min(__float_as_uint(s), __float_as_uint(ns)));
-        float s_blocked = R * s_min;
         float gap = nd - d;  // +inf when nobody is ahead
-        float S = (gap <= pth[k]) ? s_blocked : s_free;
-        // synchronous update
-        bool run = d < L;
+        // R*s_min when blocked, R*x when free (one product of the selected
+        // factor rounds exactly as the product taken in that branch)
+        float S = R * ((gap <= pth[k]) ? s_min : x);
+        // synchronous update; a parked slot computes NaN and stays parked
         float dn = d + S;
-        bool cr = run && (dn >= L);
-        cross |= cr ? (1u << k) : 0u;
-        sl.d[k] = (run && !cr) ? dn : d;
-        sl.s[k] = run ? S : s;
+        bool cr = dn >= L;
+        cross = cross + cross + (cr ? 1u : 0u);  // slot k lands on bit k
+        sl.d[k] = cr ? d : dn;
+        sl.s[k] = S;
         d_up = d;
         s_up = s;
     }
     return cross;
 }
 
-// Step 5: rank this tick's finishers (slot mask `cross`) after the `nfin`
-// earlier ones, record them, park them at +inf.  Returns the number ranked.
+// Step 5 (ranking): ranks this tick's finishers (slot mask `cross`) after
+// the `nfin` earlier ones and records them; returns the number ranked.  A
+// lone finisher needs no fraction; several are ordered by their fractions,
+// staged in the lane's (already consumed) column of the draw table.
 template <int N>
-__device__ __forceinline__ int slots_finish(Slots<N>& sl, uint32_t cross, float L, int nfin,
-                                            int& winner, uint8_t* __restrict__ row) {
-    float fr[N];
-    const bool multi = (cross & (cross - 1u)) != 0u;
-    if (multi) {
+__device__ __forceinline__ int slots_rank(const Slots<N>& sl, uint32_t cross, float L,
+                                          char* smem, uint32_t ucol, uint32_t pbase, int nfin,
+                                          int& winner, uint8_t* __restrict__ row) {
+    if ((cross & (cross - 1u)) == 0u) {
+        uint32_t rec = 0u;
 #pragma unroll
-        for (int k = 0; k < N; ++k)
-            if ((cross >> k) & 1u) fr[k] = (L - sl.d[k]) / sl.s[k];
+        for (int k = 0; k < N; ++k) rec = ((cross >> k) & 1u) ? sl.rec[k] : rec;
+        const uint32_t id = (rec - pbase) >> 5;
+        if (nfin == 0) winner = (int)id;
+        if (row) row[nfin] = (uint8_t)id;
+        return 1;
     }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if ((cross >> k) & 1u) lds_st_f32(smem, ucol + 256u * k, (L - sl.d[k]) / sl.s[k]);
     int ranked = 0;
     uint32_t rem = cross;
     while (rem) {
         int bk = -1;
         float bf = 0.0f;
-        uint32_t bid = 32u;
+        uint32_t brec = 0xFFFFFFFFu;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             if (!((rem >> k) & 1u)) continue;
-            uint32_t idk = sl.id[k];
-            float f = multi ? fr[k] : 0.0f;
-            bool better = (bk < 0) || (f < bf) || (f == bf && idk < bid);
+            const uint32_t rk = sl.rec[k];
+            const float f = lds_f32(smem, ucol + 256u * k);
+            const bool better = (bk < 0) || (f < bf) || (f == bf && rk < brec);
             bk = better ? k : bk;
             bf = better ? f : bf;
-            bid = better ? idk : bid;
+            brec = better ? rk : brec;
         }
-        int r = nfin + ranked;
+        const uint32_t bid = (brec - pbase) >> 5;
+        const int r = nfin + ranked;
         if (r == 0) winner = (int)bid;
         if (row) row[r] = (uint8_t)bid;
         ++ranked;
         rem &= ~(1u << bk);
     }
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-        if ((cross >> k) & 1u) sl.d[k] = __builtin_inff();
     return ranked;
 }
 
-// Order key of a slot: position first (non-negative floats and +inf order
-// like their bit patterns), then the competitor index.
-__device__ __forceinline__ uint64_t slot_key(float d, uint32_t id) {
-    return ((uint64_t)__float_as_uint(d) << 32) | id;
+// Step 5 (parking): the slots of mask `cross` get the parking position.
+template <int N>
+__device__ __forceinline__ void slots_park(Slots<N>& sl, uint32_t cross) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if ((cross >> k) & 1u) sl.d[k] = parked();
 }
 
-// Step 6: one bubble pass restoring (position, index) order.  Each
-// compare-exchange is branch-free (unsigned min/max of the position bit
-// patterns, selects of the rest) and is skipped when no lane of the wave
-// needs it.  Returns true (wave-uniform) if any lane swapped.  Lanes whose
-// simulation has ended are sorted too; their slots are no longer read.
+// Step 6: branch-free compare-exchange of slots k and k+1.
 template <int N>
-__device__ __forceinline__ bool slots_bubble(Slots<N>& sl) {
-    bool any = false;
+__device__ __forceinline__ void slots_cx(Slots<N>& sl, int k) {
+    const bool sw = slot_key(sl.d[k], sl.rec[k]) > slot_key(sl.d[k + 1], sl.rec[k + 1]);
+    const uint32_t a = __float_as_uint(sl.d[k]), b = __float_as_uint(sl.d[k + 1]);
+    const uint32_t ra = sl.rec[k], rb = sl.rec[k + 1];
+    const float sa = sl.s[k], sb = sl.s[k + 1];
+    sl.d[k] = __uint_as_float(sw ? b : a);
+    sl.d[k + 1] = __uint_as_float(sw ? a : b);
+    sl.rec[k] = sw ? rb : ra;
+    sl.rec[k + 1] = sw ? ra : rb;
+    sl.s[k] = sw ? sb : sa;
+    sl.s[k + 1] = sw ? sa : sb;
+}
+
+// One upward pass (k = 0 .. N-2; carries a slot up any distance).  Returns
+// true if the result may still be out of order: each slot is final once the
+// pass has left it, so the pass checks every finished neighbour pair.
+template <int N>
+__device__ __forceinline__ bool slots_pass_up(Slots<N>& sl) {
+    bool bad = false;
 #pragma unroll
     for (int k = 0; k < N - 1; ++k) {
-        bool sw = slot_key(sl.d[k], sl.id[k]) > slot_key(sl.d[k + 1], sl.id[k + 1]);
-        if (__builtin_amdgcn_ballot_w64(sw)) {
-            uint32_t a = __float_as_uint(sl.d[k]), b = __float_as_uint(sl.d[k + 1]);
-            float s0 = sw ? sl.s[k + 1] : sl.s[k];
-            float s1 = sw ? sl.s[k] : sl.s[k + 1];
-            uint32_t i0 = sw ? sl.id[k + 1] : sl.id[k];
-            uint32_t i1 = sw ? sl.id[k] : sl.id[k + 1];
-            sl.d[k] = __uint_as_float(a < b ? a : b);
-            sl.d[k + 1] = __uint_as_float(a < b ? b : a);
-            sl.s[k] = s0;
-            sl.s[k + 1] = s1;
-            sl.id[k] = i0;
-            sl.id[k + 1] = i1;
-            any = true;
-        }
+        slots_cx<N>(sl, k);
+        if (k >= 1)
+            bad |= slot_key(sl.d[k - 1], sl.rec[k - 1]) > slot_key(sl.d[k], sl.rec[k]);
     }
-    return any;
+    return bad;
 }
 
-// Step 6 in full: passes until no lane of the wave swaps (the usual tick
-// needs one pass that swaps and one that confirms).
+// One downward pass (k = N-2 .. 0; carries a slot down any distance).
+template <int N>
+__device__ __forceinline__ bool slots_pass_down(Slots<N>& sl) {
+    bool bad = false;
+#pragma unroll
+    for (int k = N - 2; k >= 0; --k) {
+        slots_cx<N>(sl, k);
+        if (k + 2 <= N - 1)
+            bad |= slot_key(sl.d[k + 1], sl.rec[k + 1]) > slot_key(sl.d[k + 2], sl.rec[k + 2]);
+    }
+    return bad;
+}
+
+// Step 6 in full: alternate passes until every active lane of the wave is
+// in order (a tick's overtakes need one pass in most lanes, two where a
+// slot moves down by more than one place).
 template <int N>
 __device__ __forceinline__ void slots_restore(Slots<N>& sl) {
-    while (slots_bubble<N>(sl)) {
+    for (;;) {
+        if (!__builtin_amdgcn_ballot_w64(slots_pass_up<N>(sl))) break;
+        if (!__builtin_amdgcn_ballot_w64(slots_pass_down<N>(sl))) break;
     }
 }
-
 
 // One generation: up to 64 simulations of one race from one state, one per
 // lane, in lockstep from tick t0.  `live` marks the lanes that hold a
 // simulation (index `sim`); `row` (or null) receives its finish order.
+// Lanes whose simulation has ended keep stepping with the others (their
+// results are no longer recorded), so the tick needs no divergent branch.
 // Winners go to the LDS histogram `hist`; competitor-steps add to `steps`.
 template <int N>
 __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t pbase,
@@ -248,27 +291,41 @@ __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32
                                                uint8_t* __restrict__ row, uint32_t* hist,
                                                unsigned long long& steps) {
     Slots<N> sl;
-    slots_reset<N>(sl, d0, s0, id0);
+    slots_reset<N>(sl, d0, s0, id0, pbase);
     uint32_t t = t0;
     int nfin = 0, winner = -1;
     while (__builtin_amdgcn_ballot_w64(live)) {
-        if (live) {
-            uint32_t cross = slots_tick<N>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
-            if (cross) {
-                int k = slots_finish<N>(sl, cross, L, nfin, winner, row);
+        const uint32_t cross = slots_tick<N>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
+        if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
+            if (live && cross) {
+                const int k = slots_rank<N>(sl, cross, L, smem, ucol, pbase, nfin, winner, row);
                 nfin += k;
                 steps += (unsigned long long)k * (t + 1 - t0);
             }
-            if (nfin >= stop_after || t + 1 - t0 >= kTickLimit) {
-                if (winner >= 0) atomicAdd(&hist[winner], 1u);
-                if (row)
-                    for (int r = nfin; r < N; ++r) row[r] = 0xFF;
-                steps += (unsigned long long)(N - nfin) * (t + 1 - t0);
-                live = false;
-            }
+            slots_park<N>(sl, cross);
+        }
+        if (live && (nfin >= stop_after || t + 1 - t0 >= kTickLimit)) {
+            if (winner >= 0) atomicAdd(&hist[winner], 1u);
+            if (row)
+                for (int r = nfin; r < N; ++r) row[r] = 0xFF;
+            steps += (unsigned long long)(N - nfin) * (t + 1 - t0);
+            live = false;
         }
         t += 1;
         slots_restore<N>(sl);
+    }
+}
+
+// Writes a lane's state in competitor order (prefix runs).
+template <int N>
+__device__ __forceinline__ void slots_store(const Slots<N>& sl, uint32_t pbase,
+                                            float* __restrict__ pos_out,
+                                            float* __restrict__ prev_out) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+        const uint32_t c = (sl.rec[k] - pbase) >> 5;
+        pos_out[c] = sl.d[k];
+        prev_out[c] = sl.s[k];
     }
 }
 

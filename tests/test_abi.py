@@ -46,8 +46,11 @@ GOOD = [[5.0, 8.0, 1.0, 0.1, 2.0]] * 3
     ([[5, 4, 1, 0, 2]], 2000.0), ([[5, 8, 0, 0, 2]], 2000.0), ([[5, 8, 1.5, 0, 2]], 2000.0),
     ([[5, 8, 1, 1.0, 2]], 2000.0), ([[5, 8, 1, 0, -1]], 2000.0), ([[np.nan, 8, 1, 0, 2]], 2000.0),
     (GOOD, 0.0), (GOOD, np.inf), ([[1e-4, 8, 1, 0, 2]], 2000.0),
+    # a nonzero scaled span below 2^-102
+    ([[1e-32, float(np.nextafter(np.float32(1e-32), np.float32(1))), 1, 0, 2]], 1e-30),
 ])
 def test_race_init_rejects(L, comp, track):
+    """Every documented rule of bbe_race_init rejects with BBE_EINVAL."""
     with pytest.raises(_bbe.BBEError) as ei:
         _bbe.Race(np.array(comp, np.float32).reshape(-1, 5), track)
     assert ei.value.code == _bbe.EINVAL

@@ -19,16 +19,16 @@ def torch():
 
 def test_trained_surrogate_gains(torch):
     from paper_2108_02419_amd import surrogate as S
-    announce("surrogate: 6000 states x 1000 sims, 60 epochs")
-    specs = inputs.surrogate_states(6000)
+    announce("surrogate: 30000 states x 500 sims, 80 epochs")
+    specs = inputs.surrogate_states(30_000)
     rng = np.random.default_rng(0)
     specs = [specs[i] for i in rng.permutation(len(specs))]
     ds = S.gen_states(specs, 4)
-    probs, _ = S.mc_probs(ds, 1000, 4, request_base=0)
+    probs, _ = S.mc_probs(ds, 500, 4, request_base=0)
     x, n, _, target = S.encode(ds, probs)
     init = inputs.surrogate_init(4)
-    net = _bbe.Mlp(init, max_batch=1024)
-    hist = S.train(net, x, n, target, epochs=60, batch=1024, lr_max=2e-3)
+    net = _bbe.Mlp(init, max_batch=512)
+    hist = S.train(net, x, n, target, epochs=80, batch=512, lr_max=2e-3)
     print(f"loss first/last epoch {hist[0]:.4f} {hist[-1]:.4f}", flush=True)
     assert hist[-1] < hist[0]
 
