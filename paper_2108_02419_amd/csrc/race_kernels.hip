@@ -22,10 +22,11 @@ constexpr int kBlock = 64 * kWaves;
 template <int N>
 struct BlockLds {
     static constexpr uint32_t kU = 0;                                      // [wave] u tables
-    static constexpr uint32_t kPar = ((kWaves * N * 256 + 1023) / 1024) * 1024;  // [wave] records
-    static constexpr uint32_t kWins = kPar + kWaves * 1024;               // u32[N]
+    static constexpr uint32_t kPar = ((kWaves * N * 256 + 1023) / 1024) * 1024;  // records
+    static constexpr uint32_t kWins = kPar + 1024;                        // u32[N]
     static constexpr uint32_t kSteps = kWins + 128;                        // u64
-    static constexpr uint32_t kBytes = kSteps + 16;
+    static constexpr uint32_t kInit = kSteps + 16;  // start state: d0, s0 (f32[N]), id0 (u8[N])
+    static constexpr uint32_t kBytes = kInit + kMaxN * 12;
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -49,12 +50,22 @@ __global__ void __launch_bounds__(kBlock)
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint32_t ucol = Lay::kU + wave * (N * 256) + lane * 4;
-    const uint32_t pbase = Lay::kPar + wave * 1024;
+    // one record table for the workgroup (every wave simulates the same
+    // race), at a compile-time offset
+    const uint32_t pbase = Lay::kPar;
     uint32_t* s_wins = reinterpret_cast<uint32_t*>(smem + Lay::kWins);
     unsigned long long* s_steps = reinterpret_cast<unsigned long long*>(smem + Lay::kSteps);
 
-    write_params<N>(smem, pbase, a.rc, lane);
-    if (threadIdx.x < N) s_wins[threadIdx.x] = 0u;
+    float* s_d0 = reinterpret_cast<float*>(smem + Lay::kInit);
+    float* s_s0 = s_d0 + kMaxN;
+    uint8_t* s_id0 = reinterpret_cast<uint8_t*>(s_s0 + kMaxN);
+    write_params<N>(smem, pbase, a.rc, (int)threadIdx.x);
+    if (threadIdx.x < N) {
+        s_wins[threadIdx.x] = 0u;
+        s_d0[threadIdx.x] = a.d0[threadIdx.x];
+        s_s0[threadIdx.x] = a.s0[threadIdx.x];
+        s_id0[threadIdx.x] = a.id0[threadIdx.x];
+    }
     if (threadIdx.x == 0) *s_steps = 0ull;
     __syncthreads();
 
@@ -67,7 +78,10 @@ __global__ void __launch_bounds__(kBlock)
         const uint64_t j = base + lane;
         const bool live = j < a.n_sims;
         uint8_t* row = (a.orders && live) ? a.orders + j * N : nullptr;
-        run_generation<N>(smem, ucol, pbase, L, a.d0, a.s0, a.id0, a.t0, live,
+        // re-read the start state from LDS each generation rather than
+        // keeping it live (in registers) across the loop
+        __asm__ volatile("" ::: "memory");
+        run_generation<N>(smem, ucol, pbase, L, s_d0, s_s0, s_id0, a.t0, live,
                           a.sim_begin + (uint32_t)j, a.request, a.k0, a.k1, a.stop_after, row,
                           s_wins, steps);
     }
