@@ -290,10 +290,12 @@ int bbe_mlp_train_step(bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
  * in bbe_state).  Slots list the competitors by position, leader first
  * (equal positions: lower index first), padded to 20; per slot 8 float32
  * features rounded to bfloat16: d/L, (L-d)/L, s/(7.5 dt), (lo+hi)/(15 dt),
- * (hi-lo)/(hi+lo), rho/0.2, theta/2 and the remaining distance over the
- * mean free speed, ((L-d)/L) / ((lo+hi)/(15 dt)) from the float32 values
- * (all 0 for padding), where dt is the tick length in seconds the race
- * parameters are expressed in.
+ * (hi-lo)/(hi+lo), rho/0.2, theta/2 and the expected remaining time
+ * rem / (spd * (1 + rho*d/L)) from the float32 values rem = (L-d)/L,
+ * spd = (lo+hi)/(15 dt) and d/L (remaining distance at the mean free speed,
+ * scaled by R_c at the midpoint of the remaining distance) (all 0 for
+ * padding), where dt is the tick length in seconds the race parameters are
+ * expressed in.
  * Outputs: x [batch][160]; slot_comp int32 [batch][20] or NULL, the
  * competitor in each slot (-1 for padding).  With probs (device double
  * [batch][20], competitor order, e.g. from bbe_batch_plan_create) the

@@ -125,9 +125,11 @@ def encode(comp, n, pos, prev, track_len, dt):
     lower index first), padded to 20.  Per slot 8 features, each one float32
     operation sequence: d/L, (L-d)/L, s/(7.5 dt), (lo+hi)/(15 dt) (the mean
     free speed over 7.5), (hi-lo)/(hi+lo), rho/0.2, theta/2, and the
-    remaining distance over the mean free speed, feature 2 / feature 4 of
-    the rounded float32 values (0 for padding), with 7.5 dt and 15 dt
-    rounded once to float32."""
+    expected remaining time rem / (spd * (1 + rho * d/L)) from the float32
+    features rem = (L-d)/L, spd = (lo+hi)/(15 dt) and d/L -- the remaining
+    distance at the mean free speed scaled by R_c at the midpoint of the
+    remaining distance, 1 + rho*(2*((L+d)/2)/L - 1) = 1 + rho*d/L -- (0 for
+    padding), with 7.5 dt and 15 dt rounded once to float32."""
     f = np.float32
     comp = np.asarray(comp, np.float32)
     B = comp.shape[0]
@@ -142,8 +144,9 @@ def encode(comp, n, pos, prev, track_len, dt):
         for r, c in enumerate(order):
             lo, hi, _, rho, theta = comp[b, c]
             d, s = f(pos[b][c]), f(prev[b][c])
-            rem, spd = f(f(L - d) / L), f(f(lo + hi) / c15)
-            X[b, r] = [f(d / L), rem, f(s / c75), spd, f(f(hi - lo) / f(hi + lo)),
-                       f(rho / f(0.2)), f(theta / f(2.0)), f(rem / spd)]
+            dl, rem, spd = f(d / L), f(f(L - d) / L), f(f(lo + hi) / c15)
+            rmid = f(f(1.0) + f(rho * dl))
+            X[b, r] = [dl, rem, f(s / c75), spd, f(f(hi - lo) / f(hi + lo)),
+                       f(rho / f(0.2)), f(theta / f(2.0)), f(rem / f(spd * rmid))]
             slot[b, r] = c
     return X.reshape(B, 160), slot

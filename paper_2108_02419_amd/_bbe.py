@@ -117,9 +117,10 @@ class Race:
         self.n = int(comp.shape[0])
         self.comp = comp
         self.track_len = float(track_len)
-        arr = (Competitor * max(self.n, 1))(*[Competitor(*map(float, r)) for r in comp])
+        # rows of 5 float32 are bbe_competitor structs
         h = ctypes.c_void_p()
-        _check(lib().bbe_race_init(arr, self.n, self.track_len, ctypes.byref(h)))
+        _check(lib().bbe_race_init(comp.ctypes.data if self.n else None, self.n, self.track_len,
+                                   ctypes.byref(h)))
         self._h = h
 
     @property
@@ -193,6 +194,64 @@ def _request_array(specs):
     return arr, keep
 
 
+_STATE_DT = np.dtype([("tick", "<u4"), ("pad", "<u4"), ("pos", "<u8"), ("prev", "<u8")])
+_REQ_DT = np.dtype([("race", "<u8"), ("state", "<u8"), ("sim_begin", "<u4"), ("n_sims", "<u4"),
+                    ("request", "<u4"), ("stop_after", "<i4")])
+assert _STATE_DT.itemsize == ctypes.sizeof(State)
+assert _REQ_DT.itemsize == ctypes.sizeof(Request)
+
+
+class RequestTable:
+    """Many requests as one packed bbe_request array, built with numpy (no
+    per-request Python objects).  ``races``: one Race per request;
+    ``n_sims``, ``requests``, ``stop_after``, ``sim_begin``: scalars or
+    per-request arrays; in-play states as ``tick`` uint32 [B] and ``pos`` /
+    ``prev`` float32 [B, m] with m >= every race's n (row r's first n
+    entries are request r's state), or all three None (start of race)."""
+
+    def __init__(self, races, n_sims, requests, stop_after=0, sim_begin=0, tick=None, pos=None,
+                 prev=None):
+        B = len(races)
+        self.races = list(races)
+        self.req = np.zeros(B, _REQ_DT)
+        self.req["race"] = np.fromiter((r.handle.value for r in self.races), np.uint64, B)
+        self.req["sim_begin"] = sim_begin
+        self.req["n_sims"] = n_sims
+        self.req["request"] = np.asarray(requests, np.int64) & 0xFFFFFFFF
+        self.req["stop_after"] = stop_after
+        self.st = self.pos = self.prev = None
+        if tick is not None:
+            self.pos = np.ascontiguousarray(pos, dtype=np.float32)
+            self.prev = np.ascontiguousarray(prev, dtype=np.float32)
+            nmax = max((r.n for r in self.races), default=0)
+            if self.pos.shape != self.prev.shape or self.pos.ndim != 2 or \
+                    self.pos.shape[0] != B or self.pos.shape[1] < nmax:
+                raise BBEError(EINVAL, "pos/prev must be [n_requests, >= n] arrays")
+            self.st = np.zeros(B, _STATE_DT)
+            self.st["tick"] = np.asarray(tick, np.uint32)
+            rows = np.arange(B, dtype=np.uint64)
+            self.st["pos"] = np.uint64(self.pos.ctypes.data) + rows * np.uint64(self.pos.strides[0])
+            self.st["prev"] = np.uint64(self.prev.ctypes.data) + \
+                rows * np.uint64(self.prev.strides[0])
+            self.req["state"] = np.uint64(self.st.ctypes.data) + \
+                rows * np.uint64(_STATE_DT.itemsize)
+
+    def __len__(self):
+        return len(self.req)
+
+    @property
+    def ptr(self):
+        return self.req.ctypes.data
+
+
+def _requests(specs):
+    """(pointer, count, keepalive) for a RequestTable or a list of specs."""
+    if isinstance(specs, RequestTable):
+        return specs.ptr, len(specs), specs
+    arr, keep = _request_array(specs)
+    return arr, len(specs), keep
+
+
 class BatchPlan:
     """A plan over uneven requests (``bbe_batch_plan_*``).  Outputs are CUDA
     tensors bound at creation: ``wins`` int64 [n_reqs, 20], optional
@@ -200,10 +259,10 @@ class BatchPlan:
 
     def __init__(self, specs, seed: int, wins, probs=None, steps=None, autotune=True,
                  stream=None):
-        arr, keep = _request_array(specs)
+        arr, n_reqs, keep = _requests(specs)
         h = ctypes.c_void_p()
         self._outs = (wins, probs, steps)
-        _check(lib().bbe_batch_plan_create(arr, len(specs), seed, _dptr(wins), _dptr(probs),
+        _check(lib().bbe_batch_plan_create(arr, n_reqs, seed, _dptr(wins), _dptr(probs),
                                            _dptr(steps), PLAN_AUTOTUNE if autotune else 0,
                                            _stream(stream), ctypes.byref(h)))
         del keep
@@ -229,11 +288,14 @@ class BatchPlan:
 
 
 def prefix_batch(specs, sims, targets, seed, tick_out, pos_out, prev_out, stream=None):
-    """Batched in-play states: specs as for BatchPlan (n_sims etc. ignored)."""
-    arr, keep = _request_array(specs)
+    """Batched in-play states: specs (a list or a RequestTable) as for
+    BatchPlan (n_sims etc. ignored)."""
+    arr, n_reqs, keep = _requests(specs)
     sims = np.ascontiguousarray(sims, dtype=np.uint32)
     targets = np.ascontiguousarray(targets, dtype=np.float32)
-    _check(lib().bbe_prefix_batch(arr, sims.ctypes.data, targets.ctypes.data, len(specs), seed,
+    if sims.shape != (n_reqs,) or targets.shape != (n_reqs,):
+        raise BBEError(EINVAL, "sims and targets need one entry per request")
+    _check(lib().bbe_prefix_batch(arr, sims.ctypes.data, targets.ctypes.data, n_reqs, seed,
                                   _dptr(tick_out), _dptr(pos_out), _dptr(prev_out),
                                   _stream(stream)))
     del keep

@@ -356,9 +356,10 @@ __global__ void encode_kernel(const EncodeArgs a) {
         }
         const float lo = comp[c * 5 + 0], hi = comp[c * 5 + 1], rho = comp[c * 5 + 3],
                     theta = comp[c * 5 + 4];
-        const float rem = (L - d) / L, spd = (lo + hi) / a.c15;
-        float f[8] = {d / L,      rem,          prev[c] / a.c75, spd, (hi - lo) / (hi + lo),
-                      rho / 0.2f, theta / 2.0f, rem / spd};
+        const float dl = d / L, rem = (L - d) / L, spd = (lo + hi) / a.c15;
+        const float rmid = 1.0f + rho * dl;  // R_c at the midpoint of the remaining distance
+        float f[8] = {dl,         rem,          prev[c] / a.c75, spd, (hi - lo) / (hi + lo),
+                      rho / 0.2f, theta / 2.0f, rem / (spd * rmid)};
         for (int j = 0; j < 8; ++j) x[r * 8 + j] = to_bf16(f[j]);
         if (a.slot) a.slot[(size_t)b * kMaxN + r] = c;
         if (a.target) a.target[(size_t)b * kMaxN + r] = (float)a.probs_in[(size_t)b * kMaxN + c];

@@ -24,14 +24,15 @@ from . import _bbe, inputs
 
 DT = inputs.CFG_SURROGATE["dt"]
 L = inputs.TRACK_LEN
-PLAN_CHUNK = 16384
+PLAN_CHUNK = 65536
 
 
 class Dataset:
-    """States (host copies), encoded features and labels (device)."""
+    """States (host copies), their races, encoded features and labels."""
 
-    def __init__(self, specs, tick, pos, prev):
+    def __init__(self, specs, races, tick, pos, prev):
         self.specs = specs
+        self.races = races
         self.tick, self.pos, self.prev = tick, pos, prev
         self.n = np.array([s.n for s in specs], np.int32)
         B = len(specs)
@@ -53,21 +54,21 @@ def gen_states(specs, seed: int) -> Dataset:
     """In-play states: each spec's race run (its prefix request, sim 0) until
     the leader reaches the spec's target -- on the GPU."""
     B = len(specs)
+    races = [_bbe.Race(s.comp, L) for s in specs]
     dev = torch.device("cuda")
     tick = torch.empty(B, dtype=torch.int32, device=dev)
     pos = torch.empty((B, 20), dtype=torch.float32, device=dev)
     prev = torch.empty((B, 20), dtype=torch.float32, device=dev)
     for a in range(0, B, PLAN_CHUNK):
-        part = specs[a:a + PLAN_CHUNK]
-        races = [_bbe.Race(s.comp, L) for s in part]
-        reqs = [(r, None, 0, 1, s.prefix_request, 0) for r, s in zip(races, part)]
-        _bbe.prefix_batch(reqs, np.zeros(len(part), np.uint32), [s.target for s in part], seed,
-                          tick[a:a + len(part)], pos[a:a + len(part)], prev[a:a + len(part)])
+        b = min(B, a + PLAN_CHUNK)
+        tab = _bbe.RequestTable(races[a:b], 1, [s.prefix_request for s in specs[a:b]])
+        _bbe.prefix_batch(tab, np.zeros(b - a, np.uint32), [s.target for s in specs[a:b]], seed,
+                          tick[a:b], pos[a:b], prev[a:b])
     torch.cuda.synchronize()
     t = tick.cpu().numpy().view(np.uint32)
     if (t == 0xFFFFFFFF).any():
         raise RuntimeError("an in-play state could not be generated")
-    return Dataset(specs, t, pos.cpu().numpy(), prev.cpu().numpy())
+    return Dataset(specs, races, t, pos.cpu().numpy(), prev.cpu().numpy())
 
 
 def mc_probs(ds: Dataset, n_sims: int, seed: int, request_base: int, stop_after: int = 1,
@@ -79,13 +80,13 @@ def mc_probs(ds: Dataset, n_sims: int, seed: int, request_base: int, stop_after:
     probs = torch.zeros((B, 20), dtype=torch.float64, device=dev)
     steps_total = 0
     for a in range(0, B, PLAN_CHUNK):
-        idx = range(a, min(B, a + PLAN_CHUNK))
-        races = [_bbe.Race(ds.specs[i].comp, L) for i in idx]
-        reqs = [(r, ds.state(i), 0, n_sims, (request_base + i) & 0x7FFFFFFF, stop_after)
-                for r, i in zip(races, idx)]
-        wins = torch.zeros((len(reqs), 20), dtype=torch.int64, device=dev)
+        b = min(B, a + PLAN_CHUNK)
+        reqs = (request_base + np.arange(a, b, dtype=np.int64)) & 0x7FFFFFFF
+        tab = _bbe.RequestTable(ds.races[a:b], n_sims, reqs, stop_after, tick=ds.tick[a:b],
+                                pos=ds.pos[a:b], prev=ds.prev[a:b])
+        wins = torch.zeros((b - a, 20), dtype=torch.int64, device=dev)
         steps = torch.zeros(1, dtype=torch.int64, device=dev)
-        plan = _bbe.BatchPlan(reqs, seed, wins, probs[a:a + len(reqs)], steps, autotune=autotune)
+        plan = _bbe.BatchPlan(tab, seed, wins, probs[a:b], steps, autotune=autotune)
         plan.launch()
         torch.cuda.synchronize()
         steps_total += int(steps.item())

@@ -100,8 +100,9 @@ def test_encoding_by_hand_and_label_invariance():
                                                   np.float32(14.0) / np.float32(1.5),
                                                   np.float32(2) / np.float32(14),
                                                   np.float32(-0.2) / np.float32(0.2), 0.5,
-                                                  np.float32(0.25) / (np.float32(14.0) /
-                                                                      np.float32(1.5))],
+                                                  np.float32(0.25) / (
+                                                      (np.float32(14.0) / np.float32(1.5)) *
+                                                      np.float32(0.85))],
                                                  np.float32))
     assert (f[3:] == 0).all()
     # relabelling the competitors permutes nothing in the encoding
