@@ -289,19 +289,18 @@ int bbe_mlp_train_step(bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
  * [batch] (competitors, 1..20), pos and prev float [batch][20] (state, as
  * in bbe_state).  Slots list the competitors by position, leader first
  * (equal positions: lower index first), padded to 20; per slot 8 float32
- * features rounded to bfloat16: d/L, (L-d)/L, s/(7.5 dt), (lo+hi)/(15 dt),
- * (hi-lo)/(hi+lo), rho/0.2, theta/2 and the expected remaining time
- * rem / (spd * (1 + rho*d/L)) from the float32 values rem = (L-d)/L,
- * spd = (lo+hi)/(15 dt) and d/L (remaining distance at the mean free speed,
- * scaled by R_c at the midpoint of the remaining distance) (all 0 for
+ * features rounded to bfloat16, positions only relative to the line or to
+ * other competitors: (L-d)/L, (d_lead-d)/(75 dt), min((d_above-d)/(7.5 dt),
+ * 4) (4 for the leader), s/(7.5 dt), (lo+hi)/(15 dt), (hi-lo)/(hi+lo),
+ * rho/0.2 and (T - T_min)/10 with T = (L-d)/((lo+hi)*0.5*(1 + rho*d/L))
+ * the expected remaining ticks and T_min the state's smallest (all 0 for
  * padding), where dt is the tick length in seconds the race parameters are
- * expressed in.
- * Outputs: x [batch][160]; slot_comp int32 [batch][20] or NULL, the
- * competitor in each slot (-1 for padding).  With probs (device double
- * [batch][20], competitor order, e.g. from bbe_batch_plan_create) the
- * matching target (device float [batch][20]) receives them in slot order,
- * 0 for padding: the training labels.  probs and target are both NULL or
- * both given.                                                                */
+ * expressed in.  Outputs: x [batch][160]; slot_comp int32 [batch][20] or
+ * NULL, the competitor in each slot (-1 for padding).  With probs (device
+ * double [batch][20], competitor order, e.g. from bbe_batch_plan_create)
+ * the matching target (device float [batch][20]) receives them in slot
+ * order, 0 for padding: the training labels.  probs and target are both
+ * NULL or both given.                                                        */
 int bbe_encode_states(const float *comp, const int32_t *n, const float *pos, const float *prev,
                       int batch, float track_len, float dt, uint16_t *x, int32_t *slot_comp,
                       const double *probs, float *target, void *stream);

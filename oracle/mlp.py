@@ -122,31 +122,48 @@ def encode(comp, n, pos, prev, track_len, dt):
     competitor index in each slot [B, 20] (-1 for padding).
 
     Slots hold the competitors by position, leader first (equal positions:
-    lower index first), padded to 20.  Per slot 8 features, each one float32
-    operation sequence: d/L, (L-d)/L, s/(7.5 dt), (lo+hi)/(15 dt) (the mean
-    free speed over 7.5), (hi-lo)/(hi+lo), rho/0.2, theta/2, and the
-    expected remaining time rem / (spd * (1 + rho * d/L)) from the float32
-    features rem = (L-d)/L, spd = (lo+hi)/(15 dt) and d/L -- the remaining
-    distance at the mean free speed scaled by R_c at the midpoint of the
-    remaining distance, 1 + rho*(2*((L+d)/2)/L - 1) = 1 + rho*d/L -- (0 for
-    padding), with 7.5 dt and 15 dt rounded once to float32."""
+    lower index first), padded to 20.  Positions enter only as distances
+    relative to other competitors or to the line, so that bfloat16 keeps
+    the gaps that decide a race.  Per slot 8 features, each one float32
+    operation sequence (v = fl(7.5 dt), w = fl(75 dt), c15 = fl(15 dt)):
+      1 rem  = (L-d)/L                       remaining distance
+      2 lead = (d_lead - d)/w                gap to the leader
+      3 gap  = min((d_up - d)/v, 4)          gap to the slot above (4 for the leader)
+      4 s/v                                  previous step
+      5 spd  = (lo+hi)/c15                   mean free step over 7.5 dt
+      6 (hi-lo)/(hi+lo)                      relative noise
+      7 rho/0.2                              responsiveness
+      8 (T - T_min)/10                       expected remaining ticks behind the best
+    with T = (L-d) / ((lo+hi)*0.5 * (1 + rho*(d/L))): the remaining distance
+    at the mean free step scaled by R_c at the midpoint of the remaining
+    distance (1 + rho*(2*((L+d)/2)/L - 1) = 1 + rho*d/L), and T_min the
+    smallest T of the state.  Padding slots are 0."""
     f = np.float32
     comp = np.asarray(comp, np.float32)
     B = comp.shape[0]
     L = f(track_len)
-    c75 = f(f(7.5) * f(dt))
+    v = f(f(7.5) * f(dt))
+    w = f(f(75.0) * f(dt))
     c15 = f(f(15.0) * f(dt))
     X = np.zeros((B, 20, 8), dtype=np.float32)
     slot = np.full((B, 20), -1, dtype=np.int32)
     for b in range(B):
         k = int(n[b])
         order = sorted(range(k), key=lambda c: (-float(pos[b][c]), c))
+        T = []
+        for c in range(k):
+            lo, hi, _, rho, _ = comp[b, c]
+            d = f(pos[b][c])
+            rmid = f(f(1.0) + f(rho * f(d / L)))
+            T.append(f(f(L - d) / f(f(f(lo + hi) * f(0.5)) * rmid)))
+        t_min = min(T) if T else f(0.0)
+        d_lead = f(pos[b][order[0]]) if k else f(0.0)
         for r, c in enumerate(order):
-            lo, hi, _, rho, theta = comp[b, c]
+            lo, hi, _, rho, _ = comp[b, c]
             d, s = f(pos[b][c]), f(prev[b][c])
-            dl, rem, spd = f(d / L), f(f(L - d) / L), f(f(lo + hi) / c15)
-            rmid = f(f(1.0) + f(rho * dl))
-            X[b, r] = [dl, rem, f(s / c75), spd, f(f(hi - lo) / f(hi + lo)),
-                       f(rho / f(0.2)), f(theta / f(2.0)), f(rem / f(spd * rmid))]
+            gap = f(4.0) if r == 0 else min(f(f(f(pos[b][order[r - 1]]) - d) / v), f(4.0))
+            X[b, r] = [f(f(L - d) / L), f(f(d_lead - d) / w), gap, f(s / v),
+                       f(f(lo + hi) / c15), f(f(hi - lo) / f(hi + lo)), f(rho / f(0.2)),
+                       f(f(T[c] - t_min) / f(10.0))]
             slot[b, r] = c
     return X.reshape(B, 160), slot

@@ -251,6 +251,7 @@ BBE_API int bbe_encode_states(const float* comp, const int32_t* n, const float* 
     a.track_len = track_len;
     a.c75 = 7.5f * dt;
     a.c15 = 15.0f * dt;
+    a.c750 = 75.0f * dt;
     a.x = x;
     a.slot = slot_comp;
     a.probs_in = probs;

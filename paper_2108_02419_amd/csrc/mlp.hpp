@@ -85,7 +85,7 @@ struct EncodeArgs {
     const float* pos;    // [B][20]
     const float* prev;   // [B][20]
     int B;
-    float track_len, c75, c15;
+    float track_len, c75, c15, c750;  // 7.5 dt, 15 dt, 75 dt
     uint16_t* x;         // [B][160]
     int32_t* slot;       // [B][20] or null
     const double* probs_in;  // [B][20] competitor order, or null

@@ -333,8 +333,16 @@ __global__ void mlp_adam_kernel(const MlpAdamArgs a) {
 }
 
 // State encoding: one thread per state.  Slots hold competitors by
-// position, leader first (equal positions: lower index first); 8 float32
-// features per slot, rounded to bfloat16; zero padding.
+// position, leader first (equal positions: lower index first).  Positions
+// enter only relative to other competitors or to the line (bfloat16 keeps
+// about 2.5 significant digits: an absolute position would lose the gaps
+// that decide a race).  8 float32 features per slot, rounded to bfloat16:
+// remaining distance (L-d)/L, gap to the leader / (75 dt), gap to the slot
+// above / (7.5 dt) capped at 4 (4 for the leader), previous step / (7.5 dt),
+// mean free step (lo+hi)/(15 dt), (hi-lo)/(hi+lo), rho/0.2, and
+// (T - T_min)/10 with T = (L-d) / ((lo+hi)*0.5 * (1 + rho*d/L)) the expected
+// remaining ticks (R_c taken at the midpoint of the remaining distance);
+// zero padding.
 __global__ void encode_kernel(const EncodeArgs a) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= a.B) return;
@@ -346,20 +354,33 @@ __global__ void encode_kernel(const EncodeArgs a) {
     for (int j = 0; j < kIn; ++j) x[j] = 0;
     if (a.slot) for (int r = 0; r < kMaxN; ++r) a.slot[(size_t)b * kMaxN + r] = -1;
     if (a.target) for (int r = 0; r < kMaxN; ++r) a.target[(size_t)b * kMaxN + r] = 0.0f;
+    if (n == 0) return;
     const float L = a.track_len;
+    int inv[kMaxN];  // slot -> competitor
+    float T[kMaxN];
+    float tmin = __builtin_inff();
     for (int c = 0; c < n; ++c) {
         const float d = pos[c];
         int r = 0;
         for (int i = 0; i < n; ++i) {
-            float di = pos[i];
+            const float di = pos[i];
             r += (di > d || (di == d && i < c)) ? 1 : 0;
         }
-        const float lo = comp[c * 5 + 0], hi = comp[c * 5 + 1], rho = comp[c * 5 + 3],
-                    theta = comp[c * 5 + 4];
-        const float dl = d / L, rem = (L - d) / L, spd = (lo + hi) / a.c15;
-        const float rmid = 1.0f + rho * dl;  // R_c at the midpoint of the remaining distance
-        float f[8] = {dl,         rem,          prev[c] / a.c75, spd, (hi - lo) / (hi + lo),
-                      rho / 0.2f, theta / 2.0f, rem / (spd * rmid)};
+        inv[r] = c;
+        const float lo = comp[c * 5 + 0], hi = comp[c * 5 + 1], rho = comp[c * 5 + 3];
+        const float rmid = 1.0f + rho * (d / L);
+        T[c] = (L - d) / (((lo + hi) * 0.5f) * rmid);
+        tmin = fminf(tmin, T[c]);
+    }
+    const float d_lead = pos[inv[0]];
+    for (int r = 0; r < n; ++r) {
+        const int c = inv[r];
+        const float d = pos[c];
+        const float lo = comp[c * 5 + 0], hi = comp[c * 5 + 1], rho = comp[c * 5 + 3];
+        const float gap = r == 0 ? 4.0f : fminf((pos[inv[r - 1]] - d) / a.c75, 4.0f);
+        const float f[8] = {(L - d) / L,         (d_lead - d) / a.c750, gap,
+                            prev[c] / a.c75,     (lo + hi) / a.c15,     (hi - lo) / (hi + lo),
+                            rho / 0.2f,          (T[c] - tmin) / 10.0f};
         for (int j = 0; j < 8; ++j) x[r * 8 + j] = to_bf16(f[j]);
         if (a.slot) a.slot[(size_t)b * kMaxN + r] = c;
         if (a.target) a.target[(size_t)b * kMaxN + r] = (float)a.probs_in[(size_t)b * kMaxN + c];

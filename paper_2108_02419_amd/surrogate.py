@@ -163,11 +163,50 @@ def errors(pred_slot, ref_slot, n):
                 tv_max=float(tv.max()))
 
 
+def state_max_err(pred_slot, ref_slot, n):
+    """Per state: max over its competitors of |pred - ref| (numpy [B])."""
+    p = pred_slot.cpu().numpy().astype(np.float64)
+    r = ref_slot.cpu().numpy().astype(np.float64)
+    mask = np.arange(20)[None, :] < n.cpu().numpy()[:, None]
+    return np.where(mask, np.abs(p - r), 0.0).max(axis=1)
+
+
+def calibrate_gate(pred_slot, ent, ref_slot, n, target):
+    """Largest entropy threshold such that every calibration state whose
+    surrogate entropy is at or below it has max abs error <= target (the
+    surrogate answers those; Monte-Carlo answers the rest); -1 if even the
+    most confident state misses the target."""
+    err = state_max_err(pred_slot, ref_slot, n)
+    e = ent.cpu().numpy().astype(np.float64)
+    order = np.argsort(e, kind="stable")
+    bad = np.nonzero(err[order] > target)[0]
+    if len(bad) == 0:
+        return float(e.max())
+    if bad[0] == 0:
+        return -1.0
+    return float(e[order[bad[0] - 1]])
+
+
+def gated_errors(pred_slot, ent, mc_slot, ref_slot, n, gate):
+    """Held-out check of a gate: share of states the surrogate answers, the
+    max error of its answers, and the max error of all answers (Monte-Carlo
+    for the rest)."""
+    es = state_max_err(pred_slot, ref_slot, n)
+    em = state_max_err(mc_slot, ref_slot, n)
+    served = ent.cpu().numpy() <= gate
+    ans = np.where(served, es, em)
+    return dict(states=int(len(es)), served_frac=float(served.mean()),
+                served_max_err=float(es[served].max()) if served.any() else 0.0,
+                answer_max_err=float(ans.max()), surrogate_max_err=float(es.max()))
+
+
 def main():
     ap = argparse.ArgumentParser(description="train and judge the surrogate")
     ap.add_argument("--states", type=int, default=200_000)
     ap.add_argument("--label-sims", type=int, default=2000)
-    ap.add_argument("--eval-states", type=int, default=400)
+    ap.add_argument("--eval-states", type=int, default=2000,
+                    help="held-out states: first half calibrates the gate, second half tests it")
+    ap.add_argument("--target-err", type=float, default=0.02)
     ap.add_argument("--judge-sims", type=int, default=1_000_000)
     ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--batch", type=int, default=4096)
@@ -212,13 +251,20 @@ def main():
     rp = {}
     for d in (4, 16, 64, 10_000):  # RP(d) bettors: d simulations each
         dprobs, _ = mc_probs(eds, d, args.seed + 2, request_base=(1 << 25) + d)
-        rp[f"rp{d}_vs_judge"] = errors(encode(eds, dprobs)[3], jt, en)
+        rp[d] = encode(eds, dprobs)[3]
     torch.cuda.synchronize()
+    half = len(eds) // 2
+    gate = calibrate_gate(pred[:half], ent[:half], jt[:half], en[:half], args.target_err)
     res = dict(train_states=len(ds), label_sims=args.label_sims, epochs=args.epochs,
                batch=args.batch, lr=args.lr, train_seconds=train_s,
                label_seconds=label_s, label_competitor_steps=steps, loss_history=hist,
                eval_states=len(eds), judge_sims=args.judge_sims,
-               surrogate_vs_judge=errors(pred, jt, en), **rp)
+               surrogate_vs_judge=errors(pred, jt, en),
+               **{f"rp{d}_vs_judge": errors(v, jt, en) for d, v in rp.items()},
+               gate=dict(target_err=args.target_err, entropy_threshold=gate,
+                         calibration_states=half,
+                         test=gated_errors(pred[half:], ent[half:], rp[10_000][half:],
+                                           jt[half:], en[half:], gate)))
     log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
     np.save(os.path.join(args.out, "params.npy"), net.params())
     with open(os.path.join(args.out, "result.json"), "w") as f:

@@ -96,16 +96,22 @@ def test_encoding_by_hand_and_label_invariance():
     X, slot = mlp.encode(comp, [3], pos, prev, 2000.0, 0.1)
     assert slot[0, :4].tolist() == [1, 0, 2, -1]  # leader first, tie by index
     f = X.reshape(20, 8)
-    np.testing.assert_array_equal(f[0], np.array([0.75, 0.25, np.float32(0.6) / np.float32(0.75),
-                                                  np.float32(14.0) / np.float32(1.5),
-                                                  np.float32(2) / np.float32(14),
-                                                  np.float32(-0.2) / np.float32(0.2), 0.5,
-                                                  np.float32(0.25) / (
-                                                      (np.float32(14.0) / np.float32(1.5)) *
-                                                      np.float32(0.85))],
-                                                 np.float32))
+    # worked by hand (dt = 0.1: step scale 0.75, leader-gap scale 7.5, speed scale 1.5);
+    # remaining ticks T = (L-d) / (mean step * (1 + rho*d/L)):
+    #   c0: 1000 / (7 * 1.05) = 136.0544218, c1: 500 / (7 * 0.85) = 84.0336134,
+    #   c2: 1000 / 7 = 142.8571429; best T is c1's
+    want = np.array([
+        # rem   lead       gap  s/v     spd     noise   rho/.2 (T - Tmin)/10
+        [0.25, 0.0,       4.0, 0.8,    9.33333, 1 / 7., -1.0, 0.0],        # c1, leader
+        [0.5,  66.666667, 4.0, 1.0,    9.33333, 2 / 7., 0.5,  5.2020808],  # c0 (gap 666 -> 4)
+        [0.5,  66.666667, 0.0, 0.666667, 9.33333, 3 / 7., 0.0, 5.8823529],  # c2, tied with c0
+    ])
+    np.testing.assert_allclose(f[:3], want, rtol=2e-6, atol=1e-7)
     assert (f[3:] == 0).all()
-    # relabelling the competitors permutes nothing in the encoding
+    # relabelling the competitors changes nothing in the encoding (no ties:
+    # tied competitors are ordered by index, and the gap feature follows it)
+    pos[0, 2] = 900.0
+    X, slot = mlp.encode(comp, [3], pos, prev, 2000.0, 0.1)
     perm = [2, 0, 1]
     comp2 = comp.copy()
     pos2, prev2 = pos.copy(), prev.copy()
@@ -113,7 +119,5 @@ def test_encoding_by_hand_and_label_invariance():
     pos2[0, :3] = pos[0, perm]
     prev2[0, :3] = prev[0, perm]
     X2, slot2 = mlp.encode(comp2, [3], pos2, prev2, 2000.0, 0.1)
-    # the tie at 1000 may swap the two tied slots; compare as a multiset of rows
-    a = sorted(map(tuple, X.reshape(20, 8)))
-    b = sorted(map(tuple, X2.reshape(20, 8)))
-    assert a == b
+    np.testing.assert_array_equal(X, X2)
+    assert [perm[c] for c in slot2[0, :3]] == slot[0, :3].tolist()
