@@ -221,19 +221,24 @@ __device__ __forceinline__ void slots_park(Slots<N>& sl, uint32_t cross) {
         if ((cross >> k) & 1u) sl.d[k] = parked();
 }
 
-// Step 6: branch-free compare-exchange of slots k and k+1.
+// Step 6: compare-exchange of slots k and k+1: three v_swap_b32 under the
+// execution mask of the lanes that need the exchange, skipped when none
+// does (the first pass of a tick exchanges most pairs in some lane, later
+// passes few).
+__device__ __forceinline__ void vswap(float& a, float& b) {
+    asm volatile("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+__device__ __forceinline__ void vswap(uint32_t& a, uint32_t& b) {
+    asm volatile("v_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+}
+
 template <int N>
 __device__ __forceinline__ void slots_cx(Slots<N>& sl, int k) {
-    const bool sw = slot_key(sl.d[k], sl.rec[k]) > slot_key(sl.d[k + 1], sl.rec[k + 1]);
-    const uint32_t a = __float_as_uint(sl.d[k]), b = __float_as_uint(sl.d[k + 1]);
-    const uint32_t ra = sl.rec[k], rb = sl.rec[k + 1];
-    const float sa = sl.s[k], sb = sl.s[k + 1];
-    sl.d[k] = __uint_as_float(sw ? b : a);
-    sl.d[k + 1] = __uint_as_float(sw ? a : b);
-    sl.rec[k] = sw ? rb : ra;
-    sl.rec[k + 1] = sw ? ra : rb;
-    sl.s[k] = sw ? sb : sa;
-    sl.s[k + 1] = sw ? sa : sb;
+    if (slot_key(sl.d[k], sl.rec[k]) > slot_key(sl.d[k + 1], sl.rec[k + 1])) {
+        vswap(sl.d[k], sl.d[k + 1]);
+        vswap(sl.rec[k], sl.rec[k + 1]);
+        vswap(sl.s[k], sl.s[k + 1]);
+    }
 }
 
 // One upward pass (k = 0 .. N-2; carries a slot up any distance).  Returns
