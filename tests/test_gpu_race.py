@@ -65,6 +65,27 @@ def test_every_competitor_count(torch, orc, n):
     _compare(torch, orc, comp, 2000.0, 333, seed=n, request=5, stop_after=max(1, n // 2))
 
 
+def test_ties_and_heavy_blocking(torch, orc):
+    """Exact position ties every tick (identical deterministic competitors),
+    long blocking chains, in-play states with tied groups, single-simulation
+    launches: the paths where slot order, the competitor-ahead carry past
+    equal positions and same-tick finishing all matter."""
+    same = np.tile(np.array([[5.0, 5.0, 1.0, 0.0, 2.0]], np.float32), (20, 1))
+    _compare(torch, orc, same, 2000.0, 130, seed=11)                 # all tied, all finish together
+    _compare(torch, orc, same[:7], 2000.0, 65, seed=12, stop_after=3)
+    rng = np.random.default_rng(77)
+    mixed = inputs.competitor_params(rng, 12)
+    mixed[0:4] = [6.0, 6.0, 1.0, 0.0, 10.0]                           # four tied deterministic runners
+    mixed[4:6] = [5.0, 8.0, 1.0, 0.1, 10.0]
+    mixed[:, 4] = 10.0                                               # long blocking range
+    _compare(torch, orc, mixed, 2000.0, 257, seed=13, request=7)
+    pos = np.array([100, 100, 100, 50, 50, 120, 0, 0, 100, 75, 50, 120], np.float32)
+    prev = np.array([3, 4, 5, 6, 2, 7, 1, 9, 6, 5, 4, 3], np.float32)
+    _compare(torch, orc, mixed, 2000.0, 129, seed=14, state=(40, pos, prev))
+    _compare(torch, orc, mixed, 2000.0, 1, seed=15, state=(40, pos, prev))
+    _compare(torch, orc, same[:3], 2000.0, 1, seed=16)
+
+
 def test_sim_offsets_and_chunking(torch, orc):
     c = inputs.start_config(inputs.CFG_START_N5)
     _compare(torch, orc, c["comp"], c["L"], 777, 9, request=3, sim_begin=123_456)
