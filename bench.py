@@ -15,11 +15,13 @@ instruction occupies its SIMD for four cycles) using the algorithmic
 instruction count per competitor-step, and takes the HBM traffic per launch
 from the committed counter profile when that profile was taken on the
 current kernel sources; the cpu_baseline object times the
-CPU oracle on a bounded sample of the same workload.  Two more objects
+CPU oracle on a bounded sample of the same workload.  Three more objects
 measure the other workloads of the path: `batch` (4096 uneven in-play
-requests in one graph-captured persistent launch) and `surrogate` (queries
+requests in one graph-captured persistent launch), `surrogate` (queries
 per second of the surrogate network against Monte-Carlo at 10^4 simulations
-per query, on the same in-play state).
+per query, on the same in-play state) and `surrogate_gated` (a network
+trained here, gated to the 0.02 error target, over a whole in-play query
+loop).
 """
 from __future__ import annotations
 
@@ -113,6 +115,8 @@ def main() -> int:
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--no-gated", action="store_true",
+                    help="skip the trained, gated surrogate leg")
     ap.add_argument("--stop-after", type=int, default=None,
                     help="finishers to resolve per simulation (default: all 20)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -225,6 +229,8 @@ def main() -> int:
         line["batch"] = batch_leg(args.batch_steps)
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg()
+    if not args.no_gated:
+        line["surrogate_gated"] = gated_leg()
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c)
     print(json.dumps(line), flush=True)
@@ -345,6 +351,45 @@ def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int =
                         "queries (encode + forward); MC: 100 queries x 10^4 sims, winner only",
             "surrogate_queries_per_s": sq, "mc_queries_per_s": mq, "speedup": sq / mq,
             "surrogate_ms_per_10k": sur_s * 1e3, "mc_ms_per_100": mc_s * 1e3}
+
+
+def gated_leg(states: int = 200_000, label_sims: int = 1000, epochs: int = 60,
+              eval_states: int = 800, judge_sims: int = 1_000_000):
+    """Surrogate vs Monte-Carlo queries per second at the error target:
+    trains a network from scratch (seeded inputs, Monte-Carlo labels, the
+    library's training kernels), calibrates its entropy gate on half of the
+    held-out states (max abs error <= 0.02 against 10^6-simulation
+    Monte-Carlo), then runs the whole in-play query loop (271 rounds x 10^4
+    bettors; gated rounds and a 1% audit answered by Monte-Carlo at 10^4
+    simulations) and reports the system's rate and its answers' error."""
+    import torch
+
+    from paper_2108_02419_amd import query_loop, surrogate
+    t0 = time.perf_counter()
+    net, res = surrogate.train_and_judge(states, label_sims, epochs, batch=1024, lr=2e-3,
+                                         seed=4, eval_states=eval_states,
+                                         judge_sims=judge_sims, rp_sims=())
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    gate = res["gate"]["entropy_threshold"]
+    loop = query_loop.run(net.params(), gate=gate, judge_sims=judge_sims)
+    return {"workload": f"surrogate trained here ({states} in-play states x {label_sims} sims, "
+                        f"{epochs} epochs), entropy gate calibrated for max abs error 0.02 on "
+                        f"{eval_states // 2} held-out states; query race n=20, "
+                        f"{loop['rounds']} rounds x {loop['bettors']} bettors; judge "
+                        f"{judge_sims} sims",
+            "system_queries_per_s": loop["system_queries_per_s"],
+            "mc_queries_per_s": loop["mc_queries_per_s"],
+            "system_speedup": loop["system_speedup"],
+            "answer_err_max": loop["answer_err"]["max"],
+            "mc_err_max": loop["mc_err"]["max"],
+            "served_frac": loop["served_frac"],
+            "surrogate_raw_speedup": loop["speedup"],
+            "surrogate_raw_err": loop["surrogate_err"],
+            "heldout": {"tv_mean": res["surrogate_vs_judge"]["tv_mean"],
+                        "max_abs": res["surrogate_vs_judge"]["max_abs"],
+                        "gate": res["gate"]},
+            "setup_s": setup_s}
 
 
 if __name__ == "__main__":

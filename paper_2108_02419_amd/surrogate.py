@@ -200,6 +200,60 @@ def gated_errors(pred_slot, ent, mc_slot, ref_slot, n, gate):
                 answer_max_err=float(ans.max()), surrogate_max_err=float(es.max()))
 
 
+def train_and_judge(states=200_000, label_sims=2000, epochs=30, batch=4096, lr=2e-3, seed=4,
+                    eval_states=2000, judge_sims=1_000_000, target_err=0.02, rp_sims=(4, 16, 64),
+                    log=None):
+    """Generates states and Monte-Carlo labels, trains a network, judges it
+    on held-out states and calibrates its Monte-Carlo fallback gate.
+    Returns (network, result dict)."""
+    log = log or (lambda m: None)
+    t0 = time.perf_counter()
+    specs = inputs.surrogate_states(states)
+    rng = np.random.default_rng(seed)
+    specs = [specs[i] for i in rng.permutation(len(specs))]
+    ds = gen_states(specs, seed)
+    log(f"{len(ds)} training states ({time.perf_counter() - t0:.1f} s)")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    probs, steps = mc_probs(ds, label_sims, seed, request_base=0)
+    ev1.record()
+    torch.cuda.synchronize()
+    label_s = ev0.elapsed_time(ev1) / 1e3
+    log(f"labels: {len(ds)} x {label_sims} sims, {steps} competitor-steps, {label_s:.1f} s "
+        f"({steps / label_s:.3e} competitor-steps/s)")
+    x, n, _, target = encode(ds, probs)
+    net = _bbe.Mlp(inputs.surrogate_init(seed), max_batch=batch)
+    t1 = time.perf_counter()
+    hist = train(net, x, n, target, epochs, batch, lr, log)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+
+    # held-out states judged by high-sample Monte-Carlo
+    espec = inputs.surrogate_states(eval_states, first=10_000_000)
+    eds = gen_states(espec, seed + 1)
+    jprobs, _ = mc_probs(eds, judge_sims, seed + 1, request_base=1 << 24)
+    ex, en, _, jt = encode(eds, jprobs)
+    pred, ent = predict(net, ex, en)
+    rp = {}
+    for d in tuple(rp_sims) + (10_000,):  # RP(d) bettors: d simulations each
+        dprobs, _ = mc_probs(eds, d, seed + 2, request_base=(1 << 25) + d)
+        rp[d] = encode(eds, dprobs)[3]
+    torch.cuda.synchronize()
+    half = len(eds) // 2
+    gate = calibrate_gate(pred[:half], ent[:half], jt[:half], en[:half], target_err)
+    res = dict(train_states=len(ds), label_sims=label_sims, epochs=epochs, batch=batch, lr=lr,
+               train_seconds=train_s, label_seconds=label_s, label_competitor_steps=steps,
+               loss_history=hist, eval_states=len(eds), judge_sims=judge_sims,
+               surrogate_vs_judge=errors(pred, jt, en),
+               **{f"rp{d}_vs_judge": errors(v, jt, en) for d, v in rp.items()},
+               gate=dict(target_err=target_err, entropy_threshold=gate,
+                         calibration_states=half,
+                         test=gated_errors(pred[half:], ent[half:], rp[10_000][half:],
+                                           jt[half:], en[half:], gate)))
+    return net, res
+
+
 def main():
     ap = argparse.ArgumentParser(description="train and judge the surrogate")
     ap.add_argument("--states", type=int, default=200_000)
@@ -220,51 +274,9 @@ def main():
         print(f"[surrogate] {msg}", flush=True)
 
     torch.cuda.set_device(0)
-    t0 = time.perf_counter()
-    specs = inputs.surrogate_states(args.states)
-    rng = np.random.default_rng(args.seed)
-    specs = [specs[i] for i in rng.permutation(len(specs))]
-    ds = gen_states(specs, args.seed)
-    log(f"{len(ds)} training states ({time.perf_counter() - t0:.1f} s)")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    probs, steps = mc_probs(ds, args.label_sims, args.seed, request_base=0)
-    ev1.record()
-    torch.cuda.synchronize()
-    label_s = ev0.elapsed_time(ev1) / 1e3
-    log(f"labels: {len(ds)} x {args.label_sims} sims, {steps} competitor-steps, {label_s:.1f} s "
-        f"({steps / label_s:.3e} competitor-steps/s)")
-    x, n, _, target = encode(ds, probs)
-    net = _bbe.Mlp(inputs.surrogate_init(args.seed), max_batch=args.batch)
-    t1 = time.perf_counter()
-    hist = train(net, x, n, target, args.epochs, args.batch, args.lr, log)
-    torch.cuda.synchronize()
-    train_s = time.perf_counter() - t1
-
-    # held-out states judged by high-sample Monte-Carlo
-    espec = inputs.surrogate_states(args.eval_states, first=10_000_000)
-    eds = gen_states(espec, args.seed + 1)
-    jprobs, jsteps = mc_probs(eds, args.judge_sims, args.seed + 1, request_base=1 << 24)
-    ex, en, _, jt = encode(eds, jprobs)
-    pred, ent = predict(net, ex, en)
-    rp = {}
-    for d in (4, 16, 64, 10_000):  # RP(d) bettors: d simulations each
-        dprobs, _ = mc_probs(eds, d, args.seed + 2, request_base=(1 << 25) + d)
-        rp[d] = encode(eds, dprobs)[3]
-    torch.cuda.synchronize()
-    half = len(eds) // 2
-    gate = calibrate_gate(pred[:half], ent[:half], jt[:half], en[:half], args.target_err)
-    res = dict(train_states=len(ds), label_sims=args.label_sims, epochs=args.epochs,
-               batch=args.batch, lr=args.lr, train_seconds=train_s,
-               label_seconds=label_s, label_competitor_steps=steps, loss_history=hist,
-               eval_states=len(eds), judge_sims=args.judge_sims,
-               surrogate_vs_judge=errors(pred, jt, en),
-               **{f"rp{d}_vs_judge": errors(v, jt, en) for d, v in rp.items()},
-               gate=dict(target_err=args.target_err, entropy_threshold=gate,
-                         calibration_states=half,
-                         test=gated_errors(pred[half:], ent[half:], rp[10_000][half:],
-                                           jt[half:], en[half:], gate)))
+    net, res = train_and_judge(args.states, args.label_sims, args.epochs, args.batch, args.lr,
+                               args.seed, args.eval_states, args.judge_sims, args.target_err,
+                               log=log)
     log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
     np.save(os.path.join(args.out, "params.npy"), net.params())
     with open(os.path.join(args.out, "result.json"), "w") as f:
