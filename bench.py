@@ -193,6 +193,20 @@ def main() -> int:
     avg_kern_s = sum(kern_ms) / len(kern_ms) / 1e3
     avg_csteps = sum(comp_steps) / len(comp_steps)
     achieved = avg_csteps * ALGO_OPS_PER_COMPETITOR_STEP / avg_kern_s
+    # the same launch with the finish-order matrix written ([n_sims][n] uint8)
+    orders = torch.empty((n_sims, n), dtype=torch.uint8, device=dev)
+    oev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(3)]
+    for k, (ea, eb) in enumerate(oev):
+        ea.record(stream)
+        _bbe.race_sim(race, n_sims, c["seed"] + k, request=c["request"],
+                      stop_after=c["stop_after"], orders=orders, wins=wins,
+                      steps=steps_t[0], stream=stream)
+        eb.record(stream)
+    torch.cuda.synchronize()
+    orders_ms = sorted(a.elapsed_time(b) for a, b in oev)[1]
+    del orders
+
     km = sorted(kern_ms)
     mean = sum(km) / len(km)
     cov = (sum((x - mean) ** 2 for x in km) / len(km)) ** 0.5 / mean if len(km) > 1 else 0.0
@@ -217,6 +231,7 @@ def main() -> int:
         "competitor_steps_per_s": csteps_per_s,
         "competitor_steps_per_step": avg_csteps,
         "kernel_ms": {"median": km[len(km) // 2], "mean": mean, "min": km[0], "cov": cov},
+        "with_orders_kernel_ms": orders_ms,
         "wall_s": wall,
         "device": {"name": torch.cuda.get_device_name(0),
                    "cus": torch.cuda.get_device_properties(0).multi_processor_count},
