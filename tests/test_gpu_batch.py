@@ -135,3 +135,42 @@ def test_full_batch_workload(torch, orc):
         _, w, _ = orc.race_sim(r.comp, L, r.n_sims, SEED, request=r.index, state=ost,
                                want_orders=False, threads=8)
         np.testing.assert_array_equal(W[i, :r.n].astype(np.uint64), w)
+
+
+def test_batch_edge_cases_and_request_table(torch, orc):
+    """Single simulations, the start line next to in-play states, n = 1 and
+    n = 20 in one batch, the top of the simulation index range; the packed
+    request table gives the same plan as the per-request path."""
+    rng = np.random.default_rng(21)
+    c1 = inputs.competitor_params(rng, 1)
+    c20 = inputs.competitor_params(rng, 20)
+    c3 = inputs.competitor_params(rng, 3)
+    st3 = orc.race_prefix(c3, L, SEED, 0x80000007, 0, 900.0)
+    races = [Race(c1, L), Race(c20, L), Race(c3, L), Race(c20, L)]
+    specs = [(races[0], None, 0, 1, 5, 0),
+             (races[1], None, 7, 65, 6, 1),
+             (races[2], st3, 2**32 - 3, 3, 7, 0),
+             (races[3], None, 0, 1, 8, 20)]
+    announce("batch edge cases")
+    plan, wins, probs, steps = _run_plan(torch, specs, SEED)
+    W = wins.cpu().numpy()
+    exp_s = 0
+    for i, (race, st, b, n_sims, req, stop) in enumerate(specs):
+        comp = race.comp
+        _, w, s = orc.race_sim(comp, L, n_sims, SEED, request=req, state=st, sim_begin=b,
+                               stop_after=stop or race.n, want_orders=False)
+        np.testing.assert_array_equal(W[i, :race.n].astype(np.uint64), w)
+        exp_s += s
+    assert int(steps.item()) == exp_s
+    # the same requests as one packed table (states as [B, 20] rows)
+    tick = np.zeros(4, np.uint32)
+    pos = np.zeros((4, 20), np.float32)
+    prev = np.zeros((4, 20), np.float32)
+    prev[:] = 1.0
+    tick[2], pos[2, :3], prev[2, :3] = st3[0], st3[1], st3[2]
+    tab = _bbe.RequestTable(races, [1, 65, 3, 1], [5, 6, 7, 8], [0, 1, 0, 20],
+                            [0, 7, 2**32 - 3, 0], tick=tick, pos=pos, prev=prev)
+    # requests 0, 1, 3 as tick 0 with every position 0: nobody is ahead of
+    # anybody, so the previous steps are never read -- the start of the race
+    _, wins2, _, steps2 = _run_plan(torch, tab, SEED)
+    assert torch.equal(wins, wins2) and torch.equal(steps, steps2)

@@ -98,3 +98,18 @@ def test_estimates_converge_like_one_over_sqrt_n(orc):
         errs.append(np.mean(e))
     ratio = errs[0] / errs[1]
     assert 2.5 < ratio < 6.5, errs  # sqrt(16) = 4
+
+
+def test_tick0_equal_positions_is_the_start(orc):
+    """At tick 0 with every competitor on the line nobody is strictly ahead
+    of anybody, so the blocked branch of Eq. 1 is never taken and the
+    previous steps are never read: such a state is the start of the race."""
+    rng = np.random.default_rng(31)
+    comp = inputs.competitor_params(rng, 9)
+    a = orc.race_sim(comp, 2000.0, 200, 4, request=2)
+    for prev in (np.ones(9, np.float32), rng.uniform(0.1, 30.0, 9).astype(np.float32)):
+        b = orc.race_sim(comp, 2000.0, 200, 4, request=2,
+                         state=(0, np.zeros(9, np.float32), prev))
+        np.testing.assert_array_equal(a[0], b[0])
+        np.testing.assert_array_equal(a[1], b[1])
+        assert a[2] == b[2]
