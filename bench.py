@@ -37,12 +37,12 @@ if ROOT not in sys.path:
 
 # Algorithmic vector work per competitor-step, in wave64 vector-instruction
 # issue slots (each 32x32->64 product is one v_mad_u64_u32, each three-way
-# xor one v_bitop3_b32): a quarter of one Philox4x32-10 block (10 products,
-# 10 xors over the block's 4 words: 5 + 5) and the draw's conversion (2),
-# Eq. 1 (R 2, free step 2, min 1, product 1, gap 1, test 1, select 1 = 9),
-# the update and finish test (3), and the competitor-ahead query with a
+# xor one v_bitop3_b32): an eighth of one Philox4x32-10 block (20 products
+# and 20 xors serve the block's 8 draws: 2.5 + 2.5), the draw's conversion
+# (1), Eq. 1 (R 2, free step 2, min 1, product 1, gap 1, test 1, select 1 =
+# 9), the update and finish test (3), and the competitor-ahead query with a
 # maintained order (carry past equal positions 3, one order check 1).
-ALGO_OPS_PER_COMPETITOR_STEP = 28.0
+ALGO_OPS_PER_COMPETITOR_STEP = 22.0
 VALU_PEAK_OPS = 256 * 4 * 16 * 2.4e9  # lane-instr/s: CUs x SIMDs x lanes/clock x clock
 
 # The counter profile of the Monte-Carlo kernel on this workload, and the

@@ -78,7 +78,7 @@ typedef struct bbe_state {
  * races whose slowest possible free step, lo*pref*(1-|rho|), would need
  * more than BBE_EXPECTED_TICK_BOUND ticks to cover the track, and
  * competitors whose scaled span pref*(hi-lo) (float32) is neither 0 nor at
- * least 2^-102 (the kernels apply the 2^-24 of the draw to the span, which
+ * least 2^-110 (the kernels apply the 2^-16 of the draw to the span, which
  * is exact only there; any sensible race is far inside).
  * Errors: BBE_EINVAL, BBE_ENOMEM.                                          */
 int bbe_race_init(const bbe_competitor *comp, int n, float track_len, bbe_race **out);
@@ -97,10 +97,11 @@ int bbe_race_n(const bbe_race *race);
  * (seed, request), each from `state` (NULL = start of race: tick 0, every
  * competitor at position 0).  The draws of competitor c in the tick that
  * starts at absolute tick t of simulation s are Philox4x32-10 with key
- * (seed & 0xffffffff, seed >> 32) and counter (t, s, request, c >> 2),
- * word c & 3.  The result of each simulation therefore depends only on
- * (race, state, seed, request, s), not on how the range is split into
- * calls.
+ * (seed & 0xffffffff, seed >> 32) and counter (t, s, request, c >> 3),
+ * word (c >> 1) & 3, its high 16 bits for even c and its low 16 bits for
+ * odd c: u = k * 2^-16.  The result of each simulation therefore depends
+ * only on (race, state, seed, request, s), not on how the range is split
+ * into calls.
  *
  * A simulation stops after the tick in which the number of finishers
  * reaches stop_after (1..n; n = full finish order, 1 = winner only).

@@ -42,7 +42,9 @@
  *   which the number of finishers reaches stop_after (every competitor that
  *   crossed during that tick is ranked).
  *   Draws: Philox4x32-10 with key (seed_lo, seed_hi) and counter
- *   (t, sim, request, c>>2); word c&3; u = (w>>8) * 2^-24.
+ *   (t, sim, request, c>>3); word w = out[(c>>1)&3]; its high half
+ *   k = w >> 16 for even c, its low half k = w & 0xffff for odd c;
+ *   u = k * 2^-16.
  *
  * All single-precision arithmetic is written one rounding per operation and
  * must be compiled with -ffp-contract=off (no fused multiply-add).
@@ -83,23 +85,27 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
-/* The uniform draw of competitor c at tick t of simulation `sim`.
- * levels == 0: the full 24-bit draw.  levels == K (a power of two): the
+/* The uniform draw of competitor c at tick t of simulation `sim`: one
+ * 16-bit half of a Philox word, so one Philox block serves 8 competitors.
+ * 16 bits resolve the free step (elo + espan*u) to espan/65536, about the
+ * spacing of float32 positions near the finish of a 2000-unit track.
+ * levels == 0: the full 16-bit draw.  levels == K (a power of two): the
  * draw truncated to K equally spaced levels {0, 1/K, ..., (K-1)/K}; used
  * only by the tests that compare against exact enumeration.             */
 static float draw_u(uint64_t seed, uint32_t t, uint32_t sim, uint32_t request,
                     int c, uint32_t levels)
 {
-    uint32_t ctr[4] = { t, sim, request, (uint32_t)c >> 2 };
+    uint32_t ctr[4] = { t, sim, request, (uint32_t)c >> 3 };
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     uint32_t out[4];
     orc_philox4x32_10(ctr, key, out);
-    uint32_t m = out[c & 3] >> 8;             /* 24 bits */
+    uint32_t w = out[(c >> 1) & 3];
+    uint32_t m = (c & 1) ? (w & 0xffffu) : (w >> 16);   /* 16 bits */
     if (levels == 0)
-        return (float)m * 0x1p-24f;
+        return (float)m * 0x1p-16f;
     int lg = 0;
     while ((1u << lg) < levels) ++lg;
-    return (float)(m >> (24 - lg)) / (float)levels;
+    return (float)(m >> (16 - lg)) / (float)levels;
 }
 
 /* ------------------------------------------------------------------ */
@@ -289,7 +295,7 @@ int orc_race_sim(int n, float L, const float *comp, uint32_t t0, const float *po
     if (state_check(&r, t0, pos, prev) != ORC_OK) return ORC_EINVAL;
     if (n_sims == 0 || (uint64_t)sim_begin + n_sims > 0x100000000ull) return ORC_EINVAL;
     if (stop_after < 1 || stop_after > n) return ORC_EINVAL;
-    if (levels != 0 && (levels > (1u << 24) || (levels & (levels - 1)) != 0)) return ORC_EINVAL;
+    if (levels != 0 && (levels > (1u << 16) || (levels & (levels - 1)) != 0)) return ORC_EINVAL;
     if (threads < 1) threads = 1;
 
     uint64_t w[ORC_MAX_N];

@@ -70,12 +70,12 @@ inline int setup_competitor(const bbe_competitor& c, float L, int idx, bbe::Race
     float two_rho = 2.0f * c.rho;
     float alpha = 1.0f - c.rho;
     float beta = two_rho / L;
-    // the kernels use espan * 2^-24, exact for 0 and for spans >= 2^-102
-    if (espan != 0.0f && !(espan >= 0x1p-102f))
-        return fail(BBE_EINVAL, "competitor %d: pref*(hi-lo) must be 0 or at least 2^-102",
+    // the kernels use espan * 2^-16, exact for 0 and for spans >= 2^-110
+    if (espan != 0.0f && !(espan >= 0x1p-110f))
+        return fail(BBE_EINVAL, "competitor %d: pref*(hi-lo) must be 0 or at least 2^-110",
                     idx);
     rc.elo[idx] = elo;
-    rc.espan24[idx] = espan * 0x1p-24f;
+    rc.espan16[idx] = espan * 0x1p-16f;
     rc.alpha[idx] = alpha;
     rc.beta[idx] = beta;
     rc.theta[idx] = c.theta;

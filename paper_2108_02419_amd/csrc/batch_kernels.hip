@@ -130,7 +130,7 @@ __device__ void run_prefix_lane(const ReqDesc& rq, char* smem, uint32_t ucol, ui
                                 float* pos_out, float* prev_out) {
     for (int c = 0; c < N; ++c) {
         float4* rec = reinterpret_cast<float4*>(smem + pbase + c * 32);
-        rec[0] = make_float4(rq.rc.elo[c], rq.rc.espan24[c], rq.rc.alpha[c], rq.rc.beta[c]);
+        rec[0] = make_float4(rq.rc.elo[c], rq.rc.espan16[c], rq.rc.alpha[c], rq.rc.beta[c]);
         rec[1] = make_float4(rq.rc.theta[c], 0.0f, 0.0f, 0.0f);
     }
     Slots<N> sl;

@@ -43,7 +43,7 @@ double expected_ticks(const bbe::ReqDesc& r) {
         last = std::min(last, (double)r.d0[k]);
     }
     for (int c = 0; c < n; ++c) {
-        double m = (double)r.rc.elo[c] + 0x1p23 * (double)r.rc.espan24[c];
+        double m = (double)r.rc.elo[c] + 0x1p15 * (double)r.rc.espan16[c];
         fast = std::max(fast, m);
         slow = std::min(slow, m);
     }

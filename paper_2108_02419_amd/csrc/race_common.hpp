@@ -19,15 +19,15 @@ constexpr uint32_t kTickLimit = 1u << 20;
 //   elo = fl(P*lo), espan = fl(P*fl(hi - lo))   free step = elo + espan*u
 //   alpha = fl(1 - rho), beta = fl(fl(2*rho)/L) R_c(d) = alpha + beta*d
 //   theta                                        blocked iff gap <= theta
-// The kernels take the draw as the integer k = w >> 8 (u = k * 2^-24) and
-// the span pre-scaled, espan24 = espan * 2^-24: a power-of-two scaling, exact
-// whenever espan is 0 or at least 2^-102 (the host rejects other spans), so
-// fl(espan24 * k) = fl(espan * u) bit for bit.
+// The kernels take the draw as the integer k (a 16-bit half of a Philox
+// word, u = k * 2^-16) and the span pre-scaled, espan16 = espan * 2^-16: a
+// power-of-two scaling, exact whenever espan is 0 or at least 2^-110 (the
+// host rejects other spans), so fl(espan16 * k) = fl(espan * u) bit for bit.
 struct RaceConst {
     float L;
     int n;
     float elo[kMaxN];
-    float espan24[kMaxN];
+    float espan16[kMaxN];
     float alpha[kMaxN];
     float beta[kMaxN];
     float theta[kMaxN];
@@ -75,10 +75,14 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
     return U4{c0, c1, c2, c3};
 }
 
-// The draw as the integer k = w >> 8 in [0, 2^24), exact in float32; the
-// uniform of the model is u = k * 2^-24.
-__device__ __forceinline__ float draw24(uint32_t w) {
-    return (float)(w >> 8);
+// The two draws of a Philox word as integers in [0, 2^16), exact in
+// float32: the high half (even competitor) and the low half (odd
+// competitor); the uniform of the model is u = k * 2^-16.
+__device__ __forceinline__ float draw_hi(uint32_t w) {
+    return (float)(w >> 16);
+}
+__device__ __forceinline__ float draw_lo(uint32_t w) {
+    return (float)(w & 0xFFFFu);
 }
 
 }  // namespace bbe

@@ -15,10 +15,11 @@
 //
 // One tick (all 64 lanes at the same absolute tick t):
 //   1. draws in competitor order: Philox4x32-10(key = seed,
-//      ctr = (t, sim, request, b)) for blocks b = 0 .. ceil(N/4)-1;
-//      competitor c takes word c&3 of block c>>2, as the integer
-//      k = w >> 8 (u = k * 2^-24); the draws go to the lane's column of an
-//      LDS table and each slot reads the draw of its own competitor;
+//      ctr = (t, sim, request, b)) for blocks b = 0 .. ceil(N/8)-1;
+//      competitor c takes word (c>>1)&3 of block c>>3, its high half for
+//      even c and its low half for odd c, as the integer k (u = k * 2^-16);
+//      the draws go to the lane's column of an LDS table and each slot
+//      reads the draw of its own competitor;
 //   2. competitor ahead: the running competitor with the smallest position
 //      greater than d_c (lowest index among equal positions); gap =
 //      fl(d_ahead - d_c), +inf if nobody is ahead;
@@ -65,13 +66,13 @@ __device__ __forceinline__ float parked() {
 }
 
 // Writes the parameter records of a race into a record block: record c =
-// (elo, espan24, alpha, beta, theta, -, -, -) at pbase + 32*c.
+// (elo, espan16, alpha, beta, theta, -, -, -) at pbase + 32*c.
 template <int N>
 __device__ __forceinline__ void write_params(char* smem, uint32_t pbase, const RaceConst& rc,
                                             int lane) {
     if (lane < N) {
         float4* rec = reinterpret_cast<float4*>(smem + pbase + lane * 32);
-        rec[0] = make_float4(rc.elo[lane], rc.espan24[lane], rc.alpha[lane], rc.beta[lane]);
+        rec[0] = make_float4(rc.elo[lane], rc.espan16[lane], rc.alpha[lane], rc.beta[lane]);
         rec[1] = make_float4(rc.theta[lane], 0.0f, 0.0f, 0.0f);
     }
 }
@@ -102,12 +103,15 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
                                                uint32_t k1) {
     // 1. draws, competitor order, into this lane's column
 #pragma unroll
-    for (int b = 0; b < (N + 3) / 4; ++b) {
-        U4 w = philox4x32_10(t, sim, request, (uint32_t)b, k0, k1);
-        if (4 * b + 0 < N) lds_st_f32(smem, ucol + (4 * b + 0) * 256, draw24(w.x));
-        if (4 * b + 1 < N) lds_st_f32(smem, ucol + (4 * b + 1) * 256, draw24(w.y));
-        if (4 * b + 2 < N) lds_st_f32(smem, ucol + (4 * b + 2) * 256, draw24(w.z));
-        if (4 * b + 3 < N) lds_st_f32(smem, ucol + (4 * b + 3) * 256, draw24(w.w));
+    for (int b = 0; b < (N + 7) / 8; ++b) {
+        const U4 w = philox4x32_10(t, sim, request, (uint32_t)b, k0, k1);
+        const uint32_t words[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 8 * b + 2 * j;
+            if (c < N) lds_st_f32(smem, ucol + c * 256, draw_hi(words[j]));
+            if (c + 1 < N) lds_st_f32(smem, ucol + (c + 1) * 256, draw_lo(words[j]));
+        }
     }
 
     // 2.-4. Slots from the top down.  Slots are in (position, index) order,

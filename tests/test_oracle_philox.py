@@ -49,17 +49,25 @@ def test_philox_output_is_not_trivial(orc):
     assert len({tuple(a), tuple(b), tuple(c)}) == 3
 
 
-def test_draws_are_top_24_bits(orc):
-    """u = (w >> 8) * 2^-24: the draws of competitor c at tick t are the
-    Philox words of counter (t, sim, request, c >> 2), word c & 3.  A race of
-    4 free competitors with lo = 1, hi = 1 + 2^-10 exposes u exactly in the
-    first step (position = 1 + 2^-10 * u is exact in float32 for u on the
-    2^-24 grid... only its top 14 bits survive), so compare those."""
-    comp = np.array([[1.0, 1.0 + 2**-10, 1, 0, 0]] * 4, dtype=np.float32)
+def test_draws_are_16_bit_halves(orc):
+    """Competitor c's draw at tick t is one 16-bit half of the Philox word
+    (c >> 1) & 3 of counter (t, sim, request, c >> 3): the high half for
+    even c, the low half for odd c; u = k * 2^-16.  A race of 8 free
+    competitors with lo = 1, hi = 1 + 2^-7 exposes u exactly in the first
+    step: position 1 + 2^-7 * k * 2^-16 = 1 + k * 2^-23 is exact in float32
+    for every k < 2^16, so all 16 bits of every draw are checked."""
+    comp = np.array([[1.0, 1.0 + 2**-7, 1, 0, 0]] * 8, dtype=np.float32)
     seed, req, sim = 0x1234_5678_9ABC_DEF0, 77, 5
-    t, pos, prev = orc.race_prefix(comp, 2000.0, seed, req, sim, target=np.nextafter(np.float32(0), np.float32(1)))
-    w = orc.philox4x32_10([0, sim, req, 0], [seed & 0xFFFFFFFF, seed >> 32])
-    u = (w >> 8).astype(np.float64) * 2.0**-24
-    expect = np.float32(1.0) + np.float32(np.float32(2**-10) * np.float32(u))
+    t, pos, prev = orc.race_prefix(comp, 2000.0, seed, req, sim,
+                                   target=np.nextafter(np.float32(0), np.float32(1)))
+    w = orc.philox4x32_10([0, sim, req, 0], [seed & 0xFFFFFFFF, seed >> 32]).astype(np.uint64)
+    k = np.array([(w[c >> 1] & 0xFFFF) if c & 1 else (w[c >> 1] >> 16) for c in range(8)])
+    expect = 1.0 + k.astype(np.float64) * 2.0**-23
     assert t == 1
-    np.testing.assert_array_equal(pos, expect.astype(np.float32))
+    np.testing.assert_array_equal(pos.astype(np.float64), expect)
+    # competitors 8.. take the block of counter word c >> 3 = 1
+    comp9 = np.array([[1.0, 1.0 + 2**-7, 1, 0, 0]] * 9, dtype=np.float32)
+    _, pos9, _ = orc.race_prefix(comp9, 2000.0, seed, req, sim,
+                                 target=np.nextafter(np.float32(0), np.float32(1)))
+    w1 = orc.philox4x32_10([0, sim, req, 1], [seed & 0xFFFFFFFF, seed >> 32]).astype(np.uint64)
+    assert pos9[8] == np.float32(1.0 + float(w1[0] >> 16) * 2.0**-23)
