@@ -155,7 +155,7 @@ int bbe_race_advance(const bbe_race *race, const bbe_state *state, uint64_t seed
                      float *pos_out, float *prev_out, void *stream);
 
 /* ------------------------------------------------------------------ */
-/* Batches of uneven requests in one persistent launch.                 */
+/* Batches of uneven requests in one graph launch.                      */
 /* ------------------------------------------------------------------ */
 
 /* One request of a batch: simulations sim_begin .. sim_begin + n_sims - 1
@@ -185,7 +185,8 @@ typedef struct bbe_batch_plan bbe_batch_plan;
  * simulations per generation, ordered by competitor count and expected
  * length, longest first) to the device, optionally autotunes, and captures
  * into a HIP graph the whole launch sequence: clear the outputs, reset the
- * work queue, run the persistent kernel, compute probabilities.
+ * work queues, run one persistent kernel per competitor count present
+ * (each instantiated for its count), compute probabilities.
  *   win_counts  device uint64[n_reqs][BBE_MAX_COMPETITORS]: row r receives
  *               request r's win counts (columns >= its n stay 0).
  *   probs       device double[n_reqs][BBE_MAX_COMPETITORS] or NULL: row r
@@ -206,7 +207,8 @@ int bbe_batch_plan_create(const bbe_request *reqs, int n_reqs, uint64_t seed,
  * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
 int bbe_batch_plan_launch(bbe_batch_plan *plan, void *stream);
 
-/* Launch shape chosen for a plan (any output pointer may be NULL). */
+/* Launch shape chosen for a plan (any output pointer may be NULL); `grid`
+ * is the largest grid among the plan's per-competitor-count kernels. */
 int bbe_batch_plan_info(const bbe_batch_plan *plan, int *waves_per_block, int *grid,
                         int *sims_per_item, int *n_items);
 
