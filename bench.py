@@ -205,6 +205,16 @@ def main() -> int:
         eb.record(stream)
     torch.cuda.synchronize()
     orders_ms = sorted(a.elapsed_time(b) for a, b in oev)[1]
+    # finish-position tallies of that matrix (place probabilities)
+    counts = torch.empty((n, n), dtype=torch.int64, device=dev)
+    ea, eb = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    _bbe.rank_counts(orders, n, counts, stream=stream)
+    ea.record(stream)
+    _bbe.rank_counts(orders, n, counts, stream=stream)
+    eb.record(stream)
+    torch.cuda.synchronize()
+    rank_counts_ms = ea.elapsed_time(eb)
+    assert int(counts.sum().item()) == n_sims * n
     del orders
 
     km = sorted(kern_ms)
@@ -232,6 +242,7 @@ def main() -> int:
         "competitor_steps_per_step": avg_csteps,
         "kernel_ms": {"median": km[len(km) // 2], "mean": mean, "min": km[0], "cov": cov},
         "with_orders_kernel_ms": orders_ms,
+        "rank_counts_ms": rank_counts_ms,
         "wall_s": wall,
         "device": {"name": torch.cuda.get_device_name(0),
                    "cus": torch.cuda.get_device_properties(0).multi_processor_count},

@@ -132,6 +132,32 @@ int bbe_race_sim(const bbe_race *race, const bbe_state *state, uint32_t sim_begi
 int bbe_win_probs(const uint64_t *win_counts, int n_rows, int n, int row_stride,
                   double *probs, void *stream);
 
+/* Finish-position tallies (paper Section 6: the finish orders of repeated
+ * runs are the outcomes whose frequencies estimate the race's PMF; place
+ * and each-way markets need more than the winner).  From a finish-order
+ * matrix as bbe_race_sim writes it (device uint8 [n_sims][n], rank-major
+ * competitor indices, 0xFF for unranked places): counts[c][r] = number of
+ * simulations in which competitor c finished at rank r (device uint64
+ * [n][n], overwritten; unranked places are not counted).  The probability
+ * of finishing in the first k is sum_{r<k} counts[c][r] / n_sims.
+ * Rules: 1 <= n <= BBE_MAX_COMPETITORS; orders may be NULL when n_sims = 0.
+ * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
+int bbe_rank_counts(const uint8_t *orders, uint32_t n_sims, int n, uint64_t *counts,
+                    void *stream);
+
+/* Largest n for bbe_order_pmf (7! = 5040 orders). */
+#define BBE_ORDER_PMF_MAX_N 7
+
+/* Frequencies of complete finish orders (paper Section 6: a PMF over the
+ * n! orders).  counts[k] (device uint64 [n!], overwritten) = number of
+ * simulations whose finish order is the k-th permutation of 0..n-1 in
+ * lexicographic order (k = 0 for 0, 1, ..., n-1); rows with an unranked
+ * place are not counted.  Input as for bbe_rank_counts.
+ * Rules: 1 <= n <= BBE_ORDER_PMF_MAX_N; orders may be NULL when n_sims = 0.
+ * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
+int bbe_order_pmf(const uint8_t *orders, uint32_t n_sims, int n, uint64_t *counts,
+                  void *stream);
+
 /* In-play state generator: advance simulation `sim` of stream (seed,
  * request) of `race` from `state` (NULL = start) until the leading
  * position is >= target, and write that state (the simulation is the same

@@ -57,6 +57,8 @@ SIGNATURES = {
     "bbe_race_sim": (_I, [_P, _P, _U32, _U32, _U64, _U32, _I, _P, _P, _P, _P]),
     "bbe_win_probs": (_I, [_P, _I, _I, _I, _P, _P]),
     "bbe_race_prefix": (_I, [_P, _P, _U64, _U32, _U32, _F, _P, _P, _P, _P]),
+    "bbe_rank_counts": (_I, [_P, _U32, _I, _P, _P]),
+    "bbe_order_pmf": (_I, [_P, _U32, _I, _P, _P]),
     "bbe_batch_plan_create": (_I, [_P, _I, _U64, _P, _P, _P, ctypes.c_uint, _P, _P]),
     "bbe_batch_plan_launch": (_I, [_P, _P]),
     "bbe_batch_plan_info": (_I, [_P, _P, _P, _P, _P]),
@@ -166,6 +168,23 @@ def win_probs(wins, probs, n: int | None = None, stream=None):
     rows, stride = w2.shape
     n = stride if n is None else n
     _check(lib().bbe_win_probs(_dptr(w2), rows, n, stride, _dptr(probs), _stream(stream)))
+
+
+ORDER_PMF_MAX_N = 7
+
+
+def rank_counts(orders, n: int, counts, stream=None):
+    """Enqueue ``bbe_rank_counts``: orders uint8 CUDA tensor [n_sims, n],
+    counts int64 CUDA tensor [n, n] (overwritten)."""
+    n_sims = int(orders.shape[0]) if orders is not None else 0
+    _check(lib().bbe_rank_counts(_dptr(orders), n_sims, n, _dptr(counts), _stream(stream)))
+
+
+def order_pmf(orders, n: int, counts, stream=None):
+    """Enqueue ``bbe_order_pmf``: orders uint8 CUDA tensor [n_sims, n],
+    counts int64 CUDA tensor [n!] (overwritten)."""
+    n_sims = int(orders.shape[0]) if orders is not None else 0
+    _check(lib().bbe_order_pmf(_dptr(orders), n_sims, n, _dptr(counts), _stream(stream)))
 
 
 def race_prefix(race: Race, seed: int, request: int, sim: int, target: float, tick_out,

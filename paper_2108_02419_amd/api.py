@@ -46,3 +46,20 @@ def prefix(race: Race, seed: int, request: int, sim: int, target: float, state=N
     _bbe.race_prefix(race, seed, request, sim, target, tick, pos, prev, state=state,
                      stream=stream)
     return tick, pos, prev
+
+
+def rank_counts(orders: torch.Tensor, n: int, stream=None) -> torch.Tensor:
+    """Finish-position counts [n, n] (int64, device) of an orders matrix:
+    entry [c, r] = simulations in which competitor c finished at rank r."""
+    counts = torch.empty((n, n), dtype=torch.int64, device=orders.device)
+    _bbe.rank_counts(orders, n, counts, stream=stream)
+    return counts
+
+
+def order_pmf(orders: torch.Tensor, n: int, stream=None) -> torch.Tensor:
+    """Counts [n!] (int64, device) of complete finish orders, indexed by the
+    lexicographic rank of the permutation."""
+    import math
+    counts = torch.empty(math.factorial(n), dtype=torch.int64, device=orders.device)
+    _bbe.order_pmf(orders, n, counts, stream=stream)
+    return counts

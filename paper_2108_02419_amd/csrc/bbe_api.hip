@@ -100,6 +100,32 @@ BBE_API int bbe_win_probs(const uint64_t* win_counts, int n_rows, int n, int row
     return ok();
 }
 
+BBE_API int bbe_rank_counts(const uint8_t* orders, uint32_t n_sims, int n, uint64_t* counts,
+                            void* stream) {
+    if (n < 1 || n > BBE_MAX_COMPETITORS)
+        return fail(BBE_EINVAL, "n = %d outside 1..%d", n, BBE_MAX_COMPETITORS);
+    if (!counts || (!orders && n_sims > 0)) return fail(BBE_EINVAL, "NULL buffer");
+    hipError_t e = bbe::launch_rank_counts(orders, n_sims, n,
+                                           reinterpret_cast<unsigned long long*>(counts),
+                                           static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching rank_counts_kernel");
+    return ok();
+}
+
+BBE_API int bbe_order_pmf(const uint8_t* orders, uint32_t n_sims, int n, uint64_t* counts,
+                          void* stream) {
+    if (n < 1 || n > BBE_ORDER_PMF_MAX_N)
+        return fail(BBE_EINVAL, "n = %d outside 1..%d", n, BBE_ORDER_PMF_MAX_N);
+    if (!counts || (!orders && n_sims > 0)) return fail(BBE_EINVAL, "NULL buffer");
+    int n_fact = 1;
+    for (int k = 2; k <= n; ++k) n_fact *= k;
+    hipError_t e = bbe::launch_order_pmf(orders, n_sims, n, n_fact,
+                                         reinterpret_cast<unsigned long long*>(counts),
+                                         static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching order_pmf_kernel");
+    return ok();
+}
+
 BBE_API int bbe_race_prefix(const bbe_race* race, const bbe_state* state, uint64_t seed,
                             uint32_t request, uint32_t sim, float target, uint32_t* tick_out,
                             float* pos_out, float* prev_out, void* stream) {

@@ -49,6 +49,12 @@ int mc_blocks_per_cu(int n);
 hipError_t launch_race_mc(const SimArgs& a, int grid, hipStream_t s);
 hipError_t launch_race_prefix(const PrefixArgs& a, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
+// Finish-order tallies over an orders matrix [n_sims][n] (see order_kernels.hip);
+// both clear their counts first.
+hipError_t launch_rank_counts(const uint8_t* orders, uint32_t n_sims, int n,
+                              unsigned long long* counts, hipStream_t s);
+hipError_t launch_order_pmf(const uint8_t* orders, uint32_t n_sims, int n, int n_fact,
+                            unsigned long long* counts, hipStream_t s);
 hipError_t launch_win_probs(const unsigned long long* wins, int n_rows, int n, int stride,
                             double* probs, hipStream_t s);
 

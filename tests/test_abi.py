@@ -83,6 +83,14 @@ def test_race_sim_rejects_before_device_work(L):
     assert L.bbe_race_sim(None, None, 0, 10, 1, 0, 3, null, null, null, null) == _bbe.EINVAL
     assert L.bbe_win_probs(None, 1, 3, 3, None, None) == _bbe.EINVAL
     assert L.bbe_race_prefix(h, None, 1, 0, 0, 2000.0, null, null, null, null) == _bbe.EINVAL
+    buf = ctypes.c_void_p(16)  # never dereferenced: rejected before any device work
+    for n in (0, 21):
+        assert L.bbe_rank_counts(buf, 10, n, buf, None) == _bbe.EINVAL
+    assert L.bbe_rank_counts(buf, 10, 5, None, None) == _bbe.EINVAL
+    assert L.bbe_rank_counts(None, 10, 5, buf, None) == _bbe.EINVAL
+    for n in (0, 8):
+        assert L.bbe_order_pmf(buf, 10, n, buf, None) == _bbe.EINVAL
+    assert L.bbe_order_pmf(None, 3, 4, buf, None) == _bbe.EINVAL
 
 
 def test_last_error_cleared_on_success(L):
