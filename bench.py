@@ -15,13 +15,14 @@ instruction occupies its SIMD for four cycles) using the algorithmic
 instruction count per competitor-step, and takes the HBM traffic per launch
 from the committed counter profile when that profile was taken on the
 current kernel sources; the cpu_baseline object times the
-CPU oracle on a bounded sample of the same workload.  Three more objects
+CPU oracle on a bounded sample of the same workload.  Four more objects
 measure the other workloads of the path: `batch` (4096 uneven in-play
 requests in one graph-captured persistent launch), `surrogate` (queries
 per second of the surrogate network against Monte-Carlo at 10^4 simulations
-per query, on the same in-play state) and `surrogate_gated` (a network
-trained here, gated to the 0.02 error target, over a whole in-play query
-loop).
+per query, on the same in-play state), `bettors` (10^4 RP(d) bettors
+re-running their dry-runs every tick of an in-play race) and
+`surrogate_gated` (a network trained here, gated to the 0.02 error
+target, over a whole in-play query loop).
 """
 from __future__ import annotations
 
@@ -117,6 +118,8 @@ def main() -> int:
     ap.add_argument("--batch-steps", type=int, default=5)
     ap.add_argument("--no-gated", action="store_true",
                     help="skip the trained, gated surrogate leg")
+    ap.add_argument("--no-bettors", action="store_true",
+                    help="skip the RP(d) bettor-population leg")
     ap.add_argument("--stop-after", type=int, default=None,
                     help="finishers to resolve per simulation (default: all 20)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -255,6 +258,8 @@ def main() -> int:
         line["batch"] = batch_leg(args.batch_steps)
     if not args.no_surrogate:
         line["surrogate"] = surrogate_leg()
+    if not args.no_bettors:
+        line["bettors"] = bettors_leg()
     if not args.no_gated:
         line["surrogate_gated"] = gated_leg()
     if not args.no_cpu_baseline:
@@ -377,6 +382,21 @@ def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int =
                         "queries (encode + forward); MC: 100 queries x 10^4 sims, winner only",
             "surrogate_queries_per_s": sq, "mc_queries_per_s": mq, "speedup": sq / mq,
             "surrogate_ms_per_10k": sur_s * 1e3, "mc_ms_per_100": mc_s * 1e3}
+
+
+def bettors_leg(n_bettors: int = 10_000, d_lo: int = 1, d_hi: int = 200):
+    """RP(d) bettors updating once per tick through a whole in-play race:
+    10^4 bettors, d log-uniform in [1, 200], one plan re-pointed at each new
+    state; GPU time of the plan launches."""
+    from paper_2108_02419_amd import bettors
+    r = bettors.run(n_bettors, d_lo, d_hi)
+    return {"workload": f"{n_bettors} RP(d) bettors, d log-uniform in [{d_lo}, {d_hi}] "
+                        f"(mean {r['d_mean']:.1f}), every tick of the n=20 query race "
+                        f"({r['rounds']} rounds)",
+            "dry_runs_per_s": r["dry_runs_per_s"], "bettor_updates_per_s": r["bettor_updates_per_s"],
+            "gpu_ms_per_round": r["gpu_ms_per_round"], "dry_runs": r["dry_runs"],
+            "host_ms_per_round_set_states": 1e3 * r["host_seconds_set_states"] / max(1, r["rounds"]),
+            "plan": r["plan"]}
 
 
 def gated_leg(states: int = 200_000, label_sims: int = 1000, epochs: int = 60,

@@ -233,6 +233,17 @@ int bbe_batch_plan_create(const bbe_request *reqs, int n_reqs, uint64_t seed,
  * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
 int bbe_batch_plan_launch(bbe_batch_plan *plan, void *stream);
 
+/* Replaces the start states of a plan's requests (the serving loop of in-play
+ * bettors: the same dry-run requests re-run from the new state of the race
+ * every time it advances, paper Sections 3 and 6), keeping the plan's
+ * graph.  `states` is a host array of the plan's n_reqs states, validated as
+ * in bbe_race_sim (all of them first: on error the plan is unchanged).  The
+ * request table is copied on `stream`, after the launches already enqueued
+ * there; launch the plan on the same stream.  The work order keeps the
+ * expected lengths of the plan's creation.
+ * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
+int bbe_batch_plan_set_states(bbe_batch_plan *plan, const bbe_state *states, void *stream);
+
 /* Launch shape chosen for a plan (any output pointer may be NULL); `grid`
  * is the largest grid among the plan's per-competitor-count kernels. */
 int bbe_batch_plan_info(const bbe_batch_plan *plan, int *waves_per_block, int *grid,

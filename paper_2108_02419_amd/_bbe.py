@@ -61,6 +61,7 @@ SIGNATURES = {
     "bbe_order_pmf": (_I, [_P, _U32, _I, _P, _P]),
     "bbe_batch_plan_create": (_I, [_P, _I, _U64, _P, _P, _P, ctypes.c_uint, _P, _P]),
     "bbe_batch_plan_launch": (_I, [_P, _P]),
+    "bbe_batch_plan_set_states": (_I, [_P, _P, _P]),
     "bbe_batch_plan_info": (_I, [_P, _P, _P, _P, _P]),
     "bbe_batch_plan_free": (None, [_P]),
     "bbe_prefix_batch": (_I, [_P, _P, _P, _I, _U64, _P, _P, _P, _P]),
@@ -280,6 +281,7 @@ class BatchPlan:
                  stream=None):
         arr, n_reqs, keep = _requests(specs)
         h = ctypes.c_void_p()
+        self.n_reqs = n_reqs
         self._outs = (wins, probs, steps)
         _check(lib().bbe_batch_plan_create(arr, n_reqs, seed, _dptr(wins), _dptr(probs),
                                            _dptr(steps), PLAN_AUTOTUNE if autotune else 0,
@@ -289,6 +291,22 @@ class BatchPlan:
 
     def launch(self, stream=None):
         _check(lib().bbe_batch_plan_launch(self._h, _stream(stream)))
+
+    def set_states(self, tick, pos, prev, stream=None):
+        """``bbe_batch_plan_set_states``: new start states for every request,
+        tick uint32 [B] and pos / prev float32 [B, m] (m >= each race's n)."""
+        pos = np.ascontiguousarray(pos, dtype=np.float32)
+        prev = np.ascontiguousarray(prev, dtype=np.float32)
+        tick = np.ascontiguousarray(tick, dtype=np.uint32)
+        B = tick.shape[0]
+        if B != self.n_reqs or pos.shape != prev.shape or pos.ndim != 2 or pos.shape[0] != B:
+            raise BBEError(EINVAL, "tick [n_requests] and pos/prev [n_requests, m] arrays")
+        st = np.zeros(B, _STATE_DT)
+        rows = np.arange(B, dtype=np.uint64)
+        st["tick"] = tick
+        st["pos"] = np.uint64(pos.ctypes.data) + rows * np.uint64(pos.strides[0])
+        st["prev"] = np.uint64(prev.ctypes.data) + rows * np.uint64(prev.strides[0])
+        _check(lib().bbe_batch_plan_set_states(self._h, st.ctypes.data, _stream(stream)))
 
     def info(self):
         v = [ctypes.c_int() for _ in range(4)]

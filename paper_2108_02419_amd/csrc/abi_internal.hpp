@@ -110,21 +110,21 @@ inline void to_slot_order(int n, const float* d, const float* s, float* d_out, f
 
 // Validates a state and writes it in slot order (state == NULL: start of
 // race, every competitor at 0, ordered by index).
-inline int check_state(const bbe_race* r, const bbe_state* st, float* d0, float* s0, uint8_t* id0,
-                uint32_t* t0) {
+inline int check_state(int n, float L, const bbe_state* st, float* d0, float* s0, uint8_t* id0,
+                       uint32_t* t0) {
     float d[BBE_MAX_COMPETITORS], s[BBE_MAX_COMPETITORS];
     if (!st) {
-        for (int c = 0; c < r->n; ++c) d[c] = s[c] = 0.0f;
+        for (int c = 0; c < n; ++c) d[c] = s[c] = 0.0f;
         *t0 = 0;
-        to_slot_order(r->n, d, s, d0, s0, id0);
+        to_slot_order(n, d, s, d0, s0, id0);
         return BBE_OK;
     }
     if (st->tick > 0xFFFFFFFFu - BBE_TICK_LIMIT)
         return fail(BBE_EINVAL, "state tick %u too large", st->tick);
     if (!st->pos || !st->prev_step) return fail(BBE_EINVAL, "state needs pos and prev_step");
-    for (int c = 0; c < r->n; ++c) {
+    for (int c = 0; c < n; ++c) {
         float p = st->pos[c], q = st->prev_step[c];
-        if (!std::isfinite(p) || p < 0.0f || !(p < r->L))
+        if (!std::isfinite(p) || p < 0.0f || !(p < L))
             return fail(BBE_EINVAL, "state: pos[%d] must be finite and in [0, L)", c);
         if (!std::isfinite(q) || !(q > 0.0f))
             return fail(BBE_EINVAL, "state: prev_step[%d] must be finite and > 0", c);
@@ -132,8 +132,13 @@ inline int check_state(const bbe_race* r, const bbe_state* st, float* d0, float*
         s[c] = q;
     }
     *t0 = st->tick;
-    to_slot_order(r->n, d, s, d0, s0, id0);
+    to_slot_order(n, d, s, d0, s0, id0);
     return BBE_OK;
+}
+
+inline int check_state(const bbe_race* r, const bbe_state* st, float* d0, float* s0, uint8_t* id0,
+                       uint32_t* t0) {
+    return check_state(r->n, r->L, st, d0, s0, id0, t0);
 }
 
 }  // namespace bbe_abi

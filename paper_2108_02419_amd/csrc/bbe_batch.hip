@@ -338,6 +338,38 @@ BBE_API int bbe_batch_plan_launch(bbe_batch_plan* plan, void* stream) {
     return ok();
 }
 
+BBE_API int bbe_batch_plan_set_states(bbe_batch_plan* plan, const bbe_state* states,
+                                      void* stream) {
+    if (!plan || !plan->exec) return fail(BBE_EINVAL, "plan is NULL");
+    if (!states) return fail(BBE_EINVAL, "states is NULL");
+    const int n_reqs = plan->n_reqs;
+    // validate every state before touching the plan
+    std::vector<float> d0((size_t)n_reqs * bbe::kMaxN), s0((size_t)n_reqs * bbe::kMaxN);
+    std::vector<uint8_t> id0((size_t)n_reqs * bbe::kMaxN);
+    std::vector<uint32_t> t0(n_reqs);
+    for (int r = 0; r < n_reqs; ++r) {
+        const bbe::ReqDesc& q = plan->host_reqs[r];
+        int rc = check_state(q.rc.n, q.rc.L, &states[r], &d0[(size_t)r * bbe::kMaxN],
+                             &s0[(size_t)r * bbe::kMaxN], &id0[(size_t)r * bbe::kMaxN], &t0[r]);
+        if (rc != BBE_OK) return fail(rc, "request %d: %s", r, g_err.c_str());
+    }
+    for (int r = 0; r < n_reqs; ++r) {
+        bbe::ReqDesc& q = plan->host_reqs[r];
+        const int n = q.rc.n;
+        std::memcpy(q.d0, &d0[(size_t)r * bbe::kMaxN], n * sizeof(float));
+        std::memcpy(q.s0, &s0[(size_t)r * bbe::kMaxN], n * sizeof(float));
+        std::memcpy(q.id0, &id0[(size_t)r * bbe::kMaxN], n);
+        q.t0 = t0[r];
+    }
+    // ordered after earlier launches on `stream`; the pageable source is
+    // consumed before the call returns
+    hipError_t e = hipMemcpyAsync(plan->d_reqs, plan->host_reqs.data(),
+                                  sizeof(bbe::ReqDesc) * n_reqs, hipMemcpyHostToDevice,
+                                  static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "copying the request table");
+    return ok();
+}
+
 BBE_API int bbe_batch_plan_info(const bbe_batch_plan* plan, int* waves_per_block, int* grid,
                                 int* sims_per_item, int* n_items) {
     if (!plan) return fail(BBE_EINVAL, "plan is NULL");

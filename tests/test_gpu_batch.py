@@ -174,3 +174,38 @@ def test_batch_edge_cases_and_request_table(torch, orc):
     # anybody, so the previous steps are never read -- the start of the race
     _, wins2, _, steps2 = _run_plan(torch, tab, SEED)
     assert torch.equal(wins, wins2) and torch.equal(steps, steps2)
+
+
+def test_plan_set_states_equals_fresh_plan(torch, orc):
+    """A plan re-pointed at new start states (the in-play serving loop)
+    gives exactly what a plan built for those states gives; a rejected
+    update leaves the plan as it was."""
+    reqs = inputs.batch_requests(n_requests=30)
+    races = [Race(r.comp, L) for r in reqs]
+    st_a = _oracle_states(orc, reqs)
+    specs = [(race, st, 0, int(min(r.n_sims, 400)), r.index, 0)
+             for r, st, race in zip(reqs, st_a, races)]
+    announce("plan set_states")
+    plan, wins, probs, steps = _run_plan(torch, specs, SEED)
+    st_b = [orc.race_prefix(r.comp, L, SEED, r.prefix_request, 0,
+                            np.float32(r.target + 0.5 * (L - r.target))) for r in reqs]
+    B = len(reqs)
+    tick = np.array([s[0] for s in st_b], np.uint32)
+    pos = np.zeros((B, 20), np.float32)
+    prev = np.ones((B, 20), np.float32)
+    for i, s in enumerate(st_b):
+        pos[i, :len(s[1])], prev[i, :len(s[2])] = s[1], s[2]
+    plan.set_states(tick, pos, prev)
+    plan.launch()
+    torch.cuda.synchronize()
+    got_w, got_s = wins.clone(), steps.clone()
+    fresh = [(race, st, 0, sp[3], sp[4], 0) for race, st, sp in zip(races, st_b, specs)]
+    _, w2, p2, s2 = _run_plan(torch, fresh, SEED)
+    assert torch.equal(got_w, w2) and torch.equal(probs, p2) and torch.equal(got_s, s2)
+    bad = pos.copy()
+    bad[3, 0] = L  # a position on the line is not an in-play state
+    with pytest.raises(_bbe.BBEError):
+        plan.set_states(tick, bad, prev)
+    plan.launch()
+    torch.cuda.synchronize()
+    assert torch.equal(wins, got_w) and torch.equal(steps, got_s)
