@@ -12,8 +12,10 @@ Contents
                    ``liborc.so`` by :func:`build`.
 ``enumerate.py``   independent pure-Python exact enumeration of tiny races.
 ``twocomp.py``     exact law of a two-competitor race by dynamic programming.
-``mlp.py``         float64 numpy reference of the surrogate network.
-``encode.py``      reference of the state encoding fed to the network.
+``mlp.py``         float64 numpy reference of the surrogate network and of
+                   the state encoding fed to it.
+``orders.py``      finish-position counts and finish-order PMF.
+``bettors.py``     the cheap in-play bettor rules (LinEx, LW, UD, ZI).
 
 Functions here take and return numpy arrays.  Competitor parameters are an
 ``[n, 5]`` float32 array of ``(lo, hi, pref, rho, theta)`` rows.
@@ -66,6 +68,8 @@ def lib() -> ctypes.CDLL:
         L.orc_race_draws.restype = i32
         L.orc_race_prefix.argtypes = [i32, f32, P, u32, P, P, u64, u32, u32, f32, P, P, P]
         L.orc_race_prefix.restype = i32
+        L.orc_race_trace.argtypes = [i32, f32, P, u32, P, P, u64, u32, u32, u32, P, P]
+        L.orc_race_trace.restype = i32
         L.orc_win_probs.argtypes = [P, i32, P]
         L.orc_win_probs.restype = i32
         L.orc_tick_limit.restype = u32
@@ -169,6 +173,24 @@ def race_prefix(comp, L, seed, request, sim, target, state=None):
     if rc != OK:
         raise OracleError(f"orc_race_prefix rejected the arguments (rc={rc})")
     return int(t_out[0]), p_out, s_out
+
+
+def race_trace(comp, L, seed, request, sim, max_rows, state=None):
+    """Positions ``[rows, n]`` of one simulated race tick by tick, from the
+    state (row 0) until just before the first tick in which a competitor
+    would reach the line, or ``max_rows`` rows."""
+    comp = _f32(comp)
+    n = comp.shape[0]
+    t0, pos, prev = 0, None, None
+    if state is not None:
+        t0, pos, prev = int(state[0]), _f32(state[1]), _f32(state[2])
+    trace = np.zeros((max_rows, n), dtype=np.float32)
+    rows = np.zeros(1, dtype=np.uint32)
+    rc = lib().orc_race_trace(n, float(L), _ptr(comp), t0, _ptr(pos), _ptr(prev), seed,
+                              request, sim, int(max_rows), _ptr(trace), _ptr(rows))
+    if rc != OK:
+        raise OracleError(f"orc_race_trace rejected the arguments (rc={rc})")
+    return trace[: int(rows[0])].copy()
 
 
 def win_probs(wins) -> np.ndarray:

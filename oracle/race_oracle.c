@@ -393,6 +393,51 @@ int orc_race_prefix(int n, float L, const float *comp, uint32_t t0, const float 
     return ORC_OK;
 }
 
+/* Positions of one simulated race tick by tick: row 0 is the given state
+ * (pos == NULL: the start), row r the positions after r ticks of
+ * simulation `sim` of `request`.  The trace ends before the first tick in
+ * which some competitor reaches the line (in-play betting on the winner
+ * closes then, Section 3), or after max_rows rows.  trace [max_rows][n];
+ * *rows_out = rows written (>= 1).                                        */
+int orc_race_trace(int n, float L, const float *comp, uint32_t t0, const float *pos,
+                   const float *prev, uint64_t seed, uint32_t request, uint32_t sim,
+                   uint32_t max_rows, float *trace, uint32_t *rows_out)
+{
+    orc_race r;
+    if (race_setup(n, L, comp, &r) != ORC_OK) return ORC_EINVAL;
+    if (!pos) t0 = 0;
+    if (state_check(&r, t0, pos, prev) != ORC_OK) return ORC_EINVAL;
+    if (max_rows < 1 || max_rows > ORC_TICK_LIMIT + 1 || !trace || !rows_out)
+        return ORC_EINVAL;
+
+    float d[ORC_MAX_N], s[ORC_MAX_N], S[ORC_MAX_N];
+    int all_running[ORC_MAX_N];
+    for (int c = 0; c < n; ++c) {
+        d[c] = pos ? pos[c] : 0.0f;
+        s[c] = pos ? prev[c] : 0.0f;
+        all_running[c] = 1;
+        trace[c] = d[c];
+    }
+    uint32_t rows = 1;
+    uint32_t t = t0;
+    while (rows < max_rows) {
+        tick_steps(&r, d, s, all_running, t, seed, request, sim, 0, NULL, NULL, S);
+        int crosses = 0;
+        for (int c = 0; c < n; ++c)
+            if (d[c] + S[c] >= L) crosses = 1;
+        if (crosses) break;
+        for (int c = 0; c < n; ++c) {
+            d[c] = d[c] + S[c];
+            s[c] = S[c];
+            trace[(size_t)rows * n + c] = d[c];
+        }
+        ++rows;
+        ++t;
+    }
+    *rows_out = rows;
+    return ORC_OK;
+}
+
 /* Frequentist win probabilities: p_c = wins_c / sum(wins) in double;
  * with no recorded win every competitor gets 1/n (an RP(0) bettor holds
  * equiprobable estimates, Section 3).                                    */
