@@ -265,6 +265,72 @@ int bbe_prefix_batch(const bbe_request *reqs, const uint32_t *sims, const float 
                      void *stream);
 
 /* ------------------------------------------------------------------ */
+/* In play: the race the bettors watch and the cheap bettor rules.      */
+/* ------------------------------------------------------------------ */
+
+/* Positions of one simulated race tick by tick (paper Section 3: the state
+ * of a race is its vector of positions, advanced by Eq. 1 every tick): row
+ * 0 is `state` (NULL = start), row r the positions after r ticks of
+ * simulation `sim` of stream (seed, request) -- the simulation bbe_race_sim
+ * runs.  The trace ends before the first tick in which a competitor would
+ * reach the line (in-play betting on the winner closes then), or after
+ * max_rows rows (1..BBE_TICK_LIMIT+1).  Device outputs: trace float
+ * [max_rows][n] (rows past the end untouched), n_rows uint32[1] (>= 1).
+ * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
+int bbe_race_trace(const bbe_race *race, const bbe_state *state, uint64_t seed,
+                   uint32_t request, uint32_t sim, uint32_t max_rows, float *trace,
+                   uint32_t *n_rows, void *stream);
+
+/* Bettor rules of paper Section 5 that read the race itself; each bettor
+ * holds a view of which competitor will win.  At trace row r (positions x,
+ * tick t0 + r):
+ *   ZI     (param ignored) a competitor drawn uniformly afresh each tick:
+ *          floor(w*n/2^32) for the first word w of the Philox4x32-10 block
+ *          with key (seed lo, seed hi) and counter (t, bettor, ~0, ~0), a
+ *          counter race draws never use;
+ *   LW     (param ignored) the leader, ties to the lowest index;
+ *   UD     (param D >= 0, finite) the runner-up (largest position after the
+ *          leader's, ties to the lowest index) while fl(x_P1 - x_P2) < D,
+ *          else the leader; LW's view when n = 1;
+ *   LinEx  (param N, an integer in 1..BBE_TICK_LIMIT) mean step over the
+ *          last w = min(N, r) ticks, held to the line: the competitor with
+ *          the least ratio fl(L - x_c) / fl(x_c - x_c(r - w)) among those
+ *          with a positive displacement (ratios compared exactly, equal ones
+ *          to the lowest index); LW's view when w = 0 or nobody moved.
+ * The RP(d) bettors of Section 3 are served by dry-run requests instead.   */
+#define BBE_BETTOR_ZI 0
+#define BBE_BETTOR_LW 1
+#define BBE_BETTOR_UD 2
+#define BBE_BETTOR_LINEX 3
+
+typedef struct bbe_bettors bbe_bettors;
+
+/* Stores a population of n_bettors (>= 1) bettors on the device: host
+ * arrays kind uint8 [n_bettors] (BBE_BETTOR_*) and param float [n_bettors].
+ * Bettor b keeps index b in the outputs of bbe_bettor_views.  Synchronous.
+ * Errors: BBE_EINVAL (unknown kind, parameter out of range), BBE_ENOMEM,
+ * BBE_EDEVICE.                                                              */
+int bbe_bettors_create(const uint8_t *kind, const float *param, int n_bettors,
+                       bbe_bettors **out);
+
+/* Releases a population (NULL is ignored). */
+void bbe_bettors_free(bbe_bettors *b);
+
+/* Bettors of each kind: per_kind uint32[4] (host), indexed by BBE_BETTOR_*. */
+int bbe_bettors_count(const bbe_bettors *b, uint32_t *per_kind);
+
+/* Views of every bettor at trace rows first_row .. first_row + n_eval - 1
+ * (first_row + n_eval <= n_rows).  Device input: trace float [n_rows][n]
+ * (e.g. from bbe_race_trace; row r at tick t0 + r; positions below
+ * track_len).  Device outputs, either may be NULL but not both: views
+ * uint8 [n_eval][n_bettors], the competitor each bettor backs; counts
+ * uint32 [n_eval][n], bettors per competitor (overwritten).  n_eval = 0 is
+ * a no-op.  Errors: BBE_EINVAL, BBE_EDEVICE.                                */
+int bbe_bettor_views(const bbe_bettors *b, const float *trace, uint32_t n_rows, int n,
+                     float track_len, uint32_t t0, uint32_t first_row, uint32_t n_eval,
+                     uint64_t seed, uint8_t *views, uint32_t *counts, void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Surrogate network: encoded in-play state -> win probabilities.       */
 /* ------------------------------------------------------------------ */
 

@@ -74,6 +74,11 @@ SIGNATURES = {
     "bbe_mlp_train_step": (_I, [_P, _P, _P, _P, _I, _F, _P, _P]),
     "bbe_encode_states": (_I, [_P, _P, _P, _P, _I, _F, _F, _P, _P, _P, _P, _P]),
     "bbe_race_advance": (_I, [_P, _P, _U64, _U32, _U32, _U32, _P, _P, _P, _P]),
+    "bbe_race_trace": (_I, [_P, _P, _U64, _U32, _U32, _U32, _P, _P, _P]),
+    "bbe_bettors_create": (_I, [_P, _P, _I, _P]),
+    "bbe_bettors_free": (None, [_P]),
+    "bbe_bettors_count": (_I, [_P, _P]),
+    "bbe_bettor_views": (_I, [_P, _P, _U32, _I, _F, _U32, _U32, _U32, _U64, _P, _P, _P]),
     "bbe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -401,3 +406,56 @@ def race_advance(race: Race, seed: int, request: int, sim: int, n_ticks: int, ti
                                   seed, request, sim, int(n_ticks), _dptr(tick_out),
                                   _dptr(pos_out), _dptr(prev_out), _stream(stream)))
     del keep
+
+
+def race_trace(race: Race, seed: int, request: int, sim: int, max_rows: int, trace, n_rows,
+               state=None, stream=None):
+    """Enqueue ``bbe_race_trace``: trace float32 CUDA tensor [max_rows, n],
+    n_rows int32 (uint32 bits) CUDA tensor [1]."""
+    st, keep = _state_struct(state, race.n)
+    _check(lib().bbe_race_trace(race.handle, ctypes.byref(st) if st is not None else None,
+                                seed, request, sim, int(max_rows), _dptr(trace), _dptr(n_rows),
+                                _stream(stream)))
+    del keep
+
+
+BETTOR_KINDS = {"ZI": 0, "LW": 1, "UD": 2, "LinEx": 3}
+
+
+class Bettors:
+    """A population of cheap in-play bettors (``bbe_bettors_*``): kinds uint8
+    (``BETTOR_KINDS``) and parameters float32, host arrays."""
+
+    def __init__(self, kinds, params):
+        k = np.ascontiguousarray(kinds, dtype=np.uint8)
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        if k.ndim != 1 or p.shape != k.shape:
+            raise BBEError(EINVAL, "kinds and params must be 1-D arrays of equal length")
+        h = ctypes.c_void_p()
+        _check(lib().bbe_bettors_create(k.ctypes.data, p.ctypes.data, int(k.shape[0]),
+                                        ctypes.byref(h)))
+        self._h = h
+        self.n = int(k.shape[0])
+
+    def per_kind(self) -> np.ndarray:
+        out = np.zeros(4, dtype=np.uint32)
+        _check(lib().bbe_bettors_count(self._h, out.ctypes.data))
+        return out
+
+    def views(self, trace, n_rows: int, track_len: float, t0: int, seed: int, first_row: int,
+              n_eval: int, views=None, counts=None, stream=None):
+        """Enqueue ``bbe_bettor_views``: trace float32 CUDA tensor [>= n_rows, n];
+        views uint8 [n_eval, n_bettors] and/or counts int32 (uint32 bits)
+        [n_eval, n] CUDA tensors."""
+        _check(lib().bbe_bettor_views(self._h, _dptr(trace), int(n_rows), int(trace.shape[1]),
+                                      float(track_len), int(t0), int(first_row), int(n_eval),
+                                      seed, _dptr(views), _dptr(counts), _stream(stream)))
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.bbe_bettors_free(h)
+        self._h = None
+
+    def __del__(self):
+        self.free()

@@ -63,3 +63,30 @@ def order_pmf(orders: torch.Tensor, n: int, stream=None) -> torch.Tensor:
     counts = torch.empty(math.factorial(n), dtype=torch.int64, device=orders.device)
     _bbe.order_pmf(orders, n, counts, stream=stream)
     return counts
+
+
+def trace(race: Race, seed: int, request: int, sim: int, max_rows: int, state=None,
+          stream=None, device=None):
+    """Positions of one simulated race tick by tick.  Returns a float32 CUDA
+    tensor [rows, n] (row 0 = the start state) -- synchronises to size it."""
+    dev = device or torch.device("cuda", torch.cuda.current_device())
+    buf = torch.empty((max_rows, race.n), dtype=torch.float32, device=dev)
+    rows = torch.empty(1, dtype=torch.int32, device=dev)
+    _bbe.race_trace(race, seed, request, sim, max_rows, buf, rows, state=state, stream=stream)
+    return buf[: int(rows.item())]
+
+
+def bettor_views(bettors, trace: torch.Tensor, track_len: float, t0: int, seed: int,
+                 first_row: int = 0, n_eval: int | None = None, want_views: bool = True,
+                 stream=None):
+    """Views [n_eval, B] (uint8) and counts [n_eval, n] (int32) of a
+    :class:`Bettors` population over rows of a trace tensor."""
+    n_rows, n = trace.shape
+    if n_eval is None:
+        n_eval = n_rows - first_row
+    views = (torch.empty((n_eval, bettors.n), dtype=torch.uint8, device=trace.device)
+             if want_views else None)
+    counts = torch.empty((n_eval, n), dtype=torch.int32, device=trace.device)
+    bettors.views(trace, n_rows, track_len, t0, seed, first_row, n_eval, views=views,
+                  counts=counts, stream=stream)
+    return views, counts

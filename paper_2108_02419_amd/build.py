@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbbe.so")
 SOURCES = ["race_kernels.hip", "batch_kernels.hip", "mlp_kernels.hip", "order_kernels.hip",
-           "bbe_api.hip", "bbe_batch.hip", "bbe_mlp.hip"]
+           "bettor_kernels.hip", "bbe_api.hip", "bbe_batch.hip", "bbe_mlp.hip",
+           "bbe_bettors.hip"]
 ARCH = os.environ.get("BBE_OFFLOAD_ARCH", "gfx950")
 
 

@@ -40,6 +40,8 @@ CFG_SURROGATE = dict(name="surrogate_train", dt=1.0, seed=4, n_lo=5, n_hi=20, p_
                      frac_lo=0.05, frac_hi=1.0, label_sims=10_000)
 CFG_QUERY = dict(name="inplay_query_loop", n=20, dt=1.0, seed=5, real_request=0xC0000000,
                  n_bettors=10_000, every=1, audit_frac=0.01, mc_sims=10_000, judge_sims=1_000_000)
+CFG_VIEWS = dict(name="views_inplay_1e5", n_bettors=100_000, seed=6, ud_d_hi=30.0, linex_n_hi=60,
+                 views_seed=7)
 
 PREFIX_REQUEST_BIT = 0x80000000  # request ids used for the runs that produce in-play states
 
@@ -105,6 +107,24 @@ def batch_requests(cfg: dict = CFG_BATCH, n_requests: int | None = None) -> list
         out.append(RequestSpec(index=r, comp=comp, remaining=rem, target=float(target),
                                n_sims=sims, prefix_request=PREFIX_REQUEST_BIT | r))
     return out
+
+
+def cheap_bettors(cfg: dict = CFG_VIEWS, n_bettors: int | None = None):
+    """Kinds (uint8: 0 ZI, 1 LW, 2 UD, 3 LinEx, a quarter each, shuffled)
+    and parameters (float32) of a population of cheap in-play bettors: UD
+    distance D uniform in [0, ud_d_hi] distance units (up to about four
+    typical steps), LinEx window N a log-uniform integer in
+    [1, linex_n_hi] ticks."""
+    rng = np.random.default_rng(cfg["seed"])
+    nb = int(n_bettors if n_bettors is not None else cfg["n_bettors"])
+    kinds = (np.arange(nb) % 4).astype(np.uint8)
+    rng.shuffle(kinds)
+    params = np.zeros(nb, dtype=np.float32)
+    ud = kinds == 2
+    params[ud] = rng.uniform(0.0, cfg["ud_d_hi"], int(ud.sum()))
+    lx = kinds == 3
+    params[lx] = np.round(np.exp(rng.uniform(0.0, math.log(cfg["linex_n_hi"]), int(lx.sum()))))
+    return kinds, params
 
 
 def surrogate_states(n_states: int, cfg: dict = CFG_SURROGATE, first: int = 0) -> list[RequestSpec]:

@@ -125,3 +125,44 @@ def test_batch_plan_rejects_before_device_work(L):
                             np.array([5000.0], np.float32).ctypes.data, 1, 1, fake_out,
                             fake_out, fake_out, null)
     assert rc == _bbe.EINVAL  # target beyond the track
+
+
+def test_bettors_reject_before_device_work(L):
+    out = ctypes.c_void_p()
+    bad = [
+        ([4], [0.0]),                      # unknown kind
+        ([3], [0.0]), ([3], [1.5]), ([3], [2.0 ** 21]), ([3], [np.nan]),  # LinEx window
+        ([2], [-1.0]), ([2], [np.inf]), ([2], [np.nan]),                  # UD distance
+        ([0, 1, 9], [0.0, 0.0, 0.0]),
+    ]
+    for kinds, params in bad:
+        k = np.array(kinds, np.uint8)
+        p = np.array(params, np.float32)
+        rc = L.bbe_bettors_create(k.ctypes.data, p.ctypes.data, len(kinds), ctypes.byref(out))
+        assert rc == _bbe.EINVAL, (kinds, params)
+        assert L.bbe_last_error().decode()
+    k = np.zeros(1, np.uint8)
+    p = np.zeros(1, np.float32)
+    assert L.bbe_bettors_create(k.ctypes.data, p.ctypes.data, 0, ctypes.byref(out)) == _bbe.EINVAL
+    assert L.bbe_bettors_create(None, p.ctypes.data, 1, ctypes.byref(out)) == _bbe.EINVAL
+    # a zeroed stand-in for a population handle: every case fails validation
+    fake = np.zeros(64, np.uint64)
+    h = ctypes.c_void_p(fake.ctypes.data)
+    buf = ctypes.c_void_p(16)  # never dereferenced
+    cases = [
+        dict(n=0), dict(n=21), dict(L=0.0), dict(L=np.inf), dict(n_rows=0),
+        dict(first_row=5, n_eval=6), dict(first_row=2**32 - 1, n_eval=2), dict(views=None, counts=None),
+    ]
+    for kw in cases:
+        a = dict(n=3, L=100.0, n_rows=10, first_row=0, n_eval=10, views=buf, counts=buf)
+        a.update(kw)
+        rc = L.bbe_bettor_views(h, buf, a["n_rows"], a["n"], a["L"], 0, a["first_row"],
+                                a["n_eval"], 1, a["views"], a["counts"], None)
+        assert rc == _bbe.EINVAL, kw
+    assert L.bbe_bettor_views(None, buf, 10, 3, 100.0, 0, 0, 1, 1, buf, buf, None) == _bbe.EINVAL
+    assert L.bbe_bettor_views(h, None, 10, 3, 100.0, 0, 0, 1, 1, buf, buf, None) == _bbe.EINVAL
+    race = _bbe.Race(np.array(GOOD, np.float32), 2000.0)
+    for rows in (0, 2**20 + 2):
+        assert L.bbe_race_trace(race.handle, None, 1, 0, 0, rows, buf, buf, None) == _bbe.EINVAL
+    assert L.bbe_race_trace(race.handle, None, 1, 0, 0, 10, None, buf, None) == _bbe.EINVAL
+    assert L.bbe_race_trace(None, None, 1, 0, 0, 10, buf, buf, None) == _bbe.EINVAL
