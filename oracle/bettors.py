@@ -16,6 +16,9 @@ tick t0 (row 0 is the state at t0).  Four rules of Section 5:
         to the line, and picks the competitor that would reach it first.
   ZI    (Zero Intelligence)  a competitor chosen uniformly at random.
 
+and the view of an RP(d) bettor (Section 3), formed from its own dry-run
+win counts: the competitor that won most of them.
+
 Readings of points Section 5 leaves open:
   * Ties in position go to the lowest competitor index, for the leader
     and for the second-placed competitor alike.
@@ -30,6 +33,8 @@ Readings of points Section 5 leaves open:
     rational comparison of the single-precision operands; equal ratios go
     to the lowest index).  If no competitor moved in the window LinEx
     holds LW's view.
+  * An RP(d) bettor's view is the competitor with the most wins among its
+    dry-runs, ties (and a bettor with no recorded win) to the lowest index.
   * ZI draws afresh at every tick: one Philox4x32-10 block with key
     (seed_lo, seed_hi) and counter (t, bettor, 0xffffffff, 0xffffffff);
     its first word w gives the competitor floor(w * n / 2^32).  The last
@@ -131,4 +136,21 @@ def views(kinds, params, trace, L: float, t0: int, seed: int, first_row: int = 0
             v = view(int(kinds[b]), float(params[b]), trace, r, L, t0, b, seed)
             out[i, b] = v
             counts[i, v] += 1
+    return out, counts
+
+
+def rp_views(wins, n: int):
+    """Views ``[B]`` (uint8) and view counts ``[n]`` (uint32) of RP(d)
+    bettors from their win counts ``[B, >= n]`` (competitors 0..n-1)."""
+    wins = np.asarray(wins)
+    B = wins.shape[0]
+    out = np.zeros(B, dtype=np.uint8)
+    counts = np.zeros(n, dtype=np.uint32)
+    for b in range(B):
+        best = 0
+        for c in range(1, n):
+            if int(wins[b, c]) > int(wins[b, best]):
+                best = c
+        out[b] = best
+        counts[best] += 1
     return out, counts

@@ -187,3 +187,13 @@ def test_trace_rows_equal_prefix_states(orc):
         np.testing.assert_array_equal(pos, tr[r])
     short = orc.race_trace(comp, L, 5, 1, 2, 4, state=state)
     np.testing.assert_array_equal(short, tr[:4])
+
+
+def test_rp_views_by_hand():
+    wins = np.array([[0, 3, 1, 3], [5, 0, 0, 0], [0, 0, 0, 0], [1, 2, 3, 4], [9, 9, 9, 99]],
+                    np.uint64)
+    v, c = B.rp_views(wins, 3)  # competitor 3 is outside the race's first 3 columns
+    assert v.tolist() == [1, 0, 0, 2, 0]
+    assert c.tolist() == [3, 1, 1]
+    v4, _ = B.rp_views(wins, 4)
+    assert v4.tolist() == [1, 0, 0, 3, 3]
