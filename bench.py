@@ -260,6 +260,7 @@ def main() -> int:
         line["surrogate"] = surrogate_leg()
     if not args.no_bettors:
         line["bettors"] = bettors_leg()
+        line["views"] = views_leg()
     if not args.no_gated:
         line["surrogate_gated"] = gated_leg()
     if not args.no_cpu_baseline:
@@ -384,19 +385,76 @@ def surrogate_leg(n_queries: int = 10_000, mc_queries: int = 100, mc_sims: int =
             "surrogate_ms_per_10k": sur_s * 1e3, "mc_ms_per_100": mc_s * 1e3}
 
 
-def bettors_leg(n_bettors: int = 10_000, d_lo: int = 1, d_hi: int = 200):
+def bettors_leg(n_bettors: int = 10_000, d_lo: int = 1, d_hi: int = 200, n_cheap: int = 100_000):
     """RP(d) bettors updating once per tick through a whole in-play race:
     10^4 bettors, d log-uniform in [1, 200], one plan re-pointed at each new
-    state; GPU time of the plan launches."""
+    state; GPU time of the plan launches.  Beside them 10^5 cheap bettors
+    (LinEx, LW, UD, ZI) re-form their views every tick from the race's
+    trace, and the RP(d) bettors' views are read off their win counts."""
     from paper_2108_02419_amd import bettors
-    r = bettors.run(n_bettors, d_lo, d_hi)
+    r = bettors.run(n_bettors, d_lo, d_hi, n_cheap=n_cheap)
     return {"workload": f"{n_bettors} RP(d) bettors, d log-uniform in [{d_lo}, {d_hi}] "
                         f"(mean {r['d_mean']:.1f}), every tick of the n=20 query race "
-                        f"({r['rounds']} rounds)",
+                        f"({r['rounds']} rounds); {n_cheap} LinEx/LW/UD/ZI bettors",
             "dry_runs_per_s": r["dry_runs_per_s"], "bettor_updates_per_s": r["bettor_updates_per_s"],
             "gpu_ms_per_round": r["gpu_ms_per_round"], "dry_runs": r["dry_runs"],
             "host_ms_per_round_set_states": 1e3 * r["host_seconds_set_states"] / max(1, r["rounds"]),
+            "views_gpu_ms_per_round": r["views_gpu_ms_per_round"],
+            "backing_winner_by_tick": r["backing_winner_by_tick"],
             "plan": r["plan"]}
+
+
+def views_leg(steps: int = 20):
+    """Views of 10^5 cheap bettors (a quarter each LinEx, LW, UD, ZI) at
+    every tick of the n=20 query race's trace, in one launch; plus the views
+    of 10^4 RP(d) bettors from their win counts."""
+    import numpy as np
+    import torch
+
+    from paper_2108_02419_amd import _bbe, api, inputs
+    q = inputs.query_race()
+    race = _bbe.Race(q["comp"], inputs.TRACK_LEN)
+    trace = api.trace(race, q["seed"], q["real_request"], 0, 1 << 16)
+    rows, n = trace.shape
+    kinds, params = inputs.cheap_bettors()
+    nb = int(kinds.size)
+    b = _bbe.Bettors(kinds, params)
+    dev = trace.device
+    views = torch.empty((rows, nb), dtype=torch.uint8, device=dev)
+    counts = torch.empty((rows, n), dtype=torch.int32, device=dev)
+    seed = inputs.CFG_VIEWS["views_seed"]
+
+    def launch():
+        b.views(trace, rows, inputs.TRACK_LEN, 0, seed, 0, rows, views=views, counts=counts)
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        for e0, e1 in evs:
+            e0.record()
+            fn()
+            e1.record()
+        torch.cuda.synchronize()
+        return float(np.median([e0.elapsed_time(e1) for e0, e1 in evs]))
+
+    ms = timed(launch)
+    n_rp = 10_000
+    rng = np.random.default_rng(2)
+    wins = torch.tensor(rng.integers(0, 50, (n_rp, 20)), dtype=torch.int64, device=dev)
+    rp_v = torch.empty(n_rp, dtype=torch.uint8, device=dev)
+    rp_c = torch.empty(n, dtype=torch.int32, device=dev)
+    rp_ms = timed(lambda: _bbe.rp_views(wins, n, views=rp_v, counts=rp_c))
+    n_views = rows * nb
+    out_bytes = n_views + rows * n * 4
+    return {"workload": f"views_inplay_1e5: {nb} cheap bettors (LinEx N 1-60, UD D 0-30, LW, ZI; "
+                        f"a quarter each) x {rows} ticks of the n=20 query race, one launch",
+            "ms_per_launch": ms, "views_per_s": n_views / (ms / 1e3),
+            "output_gb_per_s": out_bytes / (ms / 1e3) / 1e9,
+            "per_kind": [int(x) for x in b.per_kind()],
+            "rp_views_10k_ms": rp_ms}
 
 
 def gated_leg(states: int = 200_000, label_sims: int = 1000, epochs: int = 60,

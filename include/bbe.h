@@ -330,6 +330,16 @@ int bbe_bettor_views(const bbe_bettors *b, const float *trace, uint32_t n_rows, 
                      float track_len, uint32_t t0, uint32_t first_row, uint32_t n_eval,
                      uint64_t seed, uint8_t *views, uint32_t *counts, void *stream);
 
+/* Views of RP(d) bettors (paper Section 3) from their own dry-run win
+ * counts: the competitor with the most wins, ties (and rows without a win)
+ * to the lowest index.  Device input: wins uint64 [n_bettors][row_stride]
+ * (competitors 0..n-1 read; e.g. a batch plan's win counts, one request per
+ * bettor).  Device outputs, either may be NULL but not both: views uint8
+ * [n_bettors]; counts uint32 [n], bettors per competitor (overwritten).
+ * Errors: BBE_EINVAL, BBE_EDEVICE.                                          */
+int bbe_rp_views(const uint64_t *wins, int n_bettors, int n, int row_stride, uint8_t *views,
+                 uint32_t *counts, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* Surrogate network: encoded in-play state -> win probabilities.       */
 /* ------------------------------------------------------------------ */

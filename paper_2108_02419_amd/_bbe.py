@@ -79,6 +79,7 @@ SIGNATURES = {
     "bbe_bettors_free": (None, [_P]),
     "bbe_bettors_count": (_I, [_P, _P]),
     "bbe_bettor_views": (_I, [_P, _P, _U32, _I, _F, _U32, _U32, _U32, _U64, _P, _P, _P]),
+    "bbe_rp_views": (_I, [_P, _I, _I, _I, _P, _P, _P]),
     "bbe_last_error": (ctypes.c_char_p, []),
 }
 
@@ -459,3 +460,10 @@ class Bettors:
 
     def __del__(self):
         self.free()
+
+
+def rp_views(wins, n: int, views=None, counts=None, stream=None):
+    """Enqueue ``bbe_rp_views``: wins int64 CUDA tensor [B, stride]; views
+    uint8 [B] and/or counts int32 (uint32 bits) [n]."""
+    _check(lib().bbe_rp_views(_dptr(wins), int(wins.shape[0]), int(n), int(wins.shape[1]),
+                              _dptr(views), _dptr(counts), _stream(stream)))

@@ -90,3 +90,12 @@ def bettor_views(bettors, trace: torch.Tensor, track_len: float, t0: int, seed: 
     bettors.views(trace, n_rows, track_len, t0, seed, first_row, n_eval, views=views,
                   counts=counts, stream=stream)
     return views, counts
+
+
+def rp_views(wins: torch.Tensor, n: int, stream=None):
+    """Views [B] (uint8) and counts [n] (int32) of RP(d) bettors from their
+    win counts [B, stride] (int64)."""
+    views = torch.empty(wins.shape[0], dtype=torch.uint8, device=wins.device)
+    counts = torch.empty(n, dtype=torch.int32, device=wins.device)
+    _bbe.rp_views(wins, n, views=views, counts=counts, stream=stream)
+    return views, counts

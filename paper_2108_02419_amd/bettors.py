@@ -4,10 +4,13 @@ the race in play once per tick (once per second) from its own d dry-runs
 once per second need 15000 x B dry-runs for a five-minute race).  One batch
 plan serves all bettors for the whole race: each round only the start state
 of their requests changes (bbe_batch_plan_set_states), and the plan's graph
-is launched again.  Orchestration only -- every simulation runs in the
-library's kernels.
+is launched again.  Alongside them a population of cheap bettors (Section
+5: LinEx, LW, UD, ZI) re-forms its views every round from the trace of the
+race in play, and each RP(d) bettor's view is the competitor that won most
+of its dry-runs.  Orchestration only -- every simulation and every view
+runs in the library's kernels.
 
-    python -m paper_2108_02419_amd.bettors --bettors 10000 --d-lo 1 --d-hi 200
+    python -m paper_2108_02419_amd.bettors --bettors 10000 --d-lo 1 --d-hi 200 --cheap 100000
 """
 from __future__ import annotations
 
@@ -20,7 +23,7 @@ import time
 import numpy as np
 import torch
 
-from . import _bbe, inputs
+from . import _bbe, api, inputs
 
 L = inputs.TRACK_LEN
 
@@ -32,8 +35,11 @@ def bettor_sims(n_bettors: int, d_lo: int, d_hi: int, seed: int) -> np.ndarray:
     return np.minimum(np.floor(np.exp(u)).astype(np.int64), d_hi).clip(d_lo)
 
 
+KIND_NAMES = ("ZI", "LW", "UD", "LinEx")
+
+
 def run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=None, judge_every=0,
-        judge_sims=1_000_000, log=print):
+        judge_sims=1_000_000, n_cheap=0, report_every=25, log=print):
     cfg = inputs.CFG_QUERY
     q = inputs.query_race(cfg)
     comp, seed, real_req = q["comp"], q["seed"], q["real_request"]
@@ -54,6 +60,22 @@ def run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=None, judge_ever
         return (tick, pos_t.cpu().numpy().copy(), prev_t.cpu().numpy().copy())
 
     state = advance(None)
+    # the race in play, tick by tick, for the cheap bettors; its rows are the
+    # states the loop below reaches with bbe_race_advance
+    trace = api.trace(race, seed, real_req, 0, 1 << 16)
+    n_rows = int(trace.shape[0])
+    if not np.array_equal(trace[every].cpu().numpy(), state[1]):
+        raise RuntimeError("race trace and advanced state disagree")
+    winner = int(torch.argmax(api.mc(race, 1, seed, request=real_req, stop_after=1)["wins"]))
+    cheap = None
+    if n_cheap:
+        kinds, params = inputs.cheap_bettors(n_bettors=n_cheap)
+        cheap = _bbe.Bettors(kinds, params)
+        cheap_views = torch.empty((1, n_cheap), dtype=torch.uint8, device=dev)
+        cheap_counts = torch.empty((1, n), dtype=torch.int32, device=dev)
+    rp_views = torch.empty(n_bettors, dtype=torch.uint8, device=dev)
+    rp_counts = torch.empty(n, dtype=torch.int32, device=dev)
+    backing = {}
     wins = torch.zeros((n_bettors, 20), dtype=torch.int64, device=dev)
     probs = torch.zeros((n_bettors, 20), dtype=torch.float64, device=dev)
     steps = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -65,7 +87,8 @@ def run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=None, judge_ever
     plan = _bbe.BatchPlan(tab, seed + 3, wins, probs, steps, autotune=True)
     setup_s = time.perf_counter() - t_setup
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    gpu_s = host_s = 0.0
+    e2 = torch.cuda.Event(enable_timing=True)
+    gpu_s = host_s = views_s = 0.0
     rounds, dry_runs, csteps = 0, 0, 0
     judged = []
     while state is not None and (max_rounds is None or rounds < max_rounds):
@@ -78,8 +101,22 @@ def run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=None, judge_ever
         e0.record()
         plan.launch()
         e1.record()
+        row = (rounds + 1) * every
+        _bbe.rp_views(wins, n, views=rp_views, counts=rp_counts)
+        if cheap is not None and row < n_rows:
+            cheap.views(trace, n_rows, L, 0, inputs.CFG_VIEWS["views_seed"], row, 1,
+                        views=cheap_views, counts=cheap_counts)
+        e2.record()
         torch.cuda.synchronize()
         gpu_s += e0.elapsed_time(e1) / 1e3
+        views_s += e1.elapsed_time(e2) / 1e3
+        if report_every and rounds % report_every == 0:
+            frac = {"RP": float((rp_views == winner).float().mean())}
+            if cheap is not None and row < n_rows:
+                cv = cheap_views[0].cpu().numpy()
+                for k, name in enumerate(KIND_NAMES):
+                    frac[name] = float((cv[kinds == k] == winner).mean())
+            backing[int(state[0])] = frac
         csteps += int(steps.item())
         dry_runs += int(d.sum())
         rounds += 1
@@ -90,7 +127,9 @@ def run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=None, judge_ever
                dry_runs=dry_runs, competitor_steps=csteps, gpu_seconds=gpu_s,
                host_seconds_set_states=host_s, plan_setup_seconds=setup_s,
                dry_runs_per_s=dry_runs / gpu_s, bettor_updates_per_s=rounds * n_bettors / gpu_s,
-               gpu_ms_per_round=1e3 * gpu_s / max(1, rounds), plan=plan.info())
+               gpu_ms_per_round=1e3 * gpu_s / max(1, rounds), plan=plan.info(),
+               cheap_bettors=n_cheap, views_gpu_ms_per_round=1e3 * views_s / max(1, rounds),
+               winner=winner, backing_winner_by_tick=backing)
     if judged:
         res["rp_error_by_d"] = _merge(judged)
     plan.free()
@@ -134,12 +173,13 @@ def main():
     ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--max-rounds", type=int, default=None)
     ap.add_argument("--judge-every", type=int, default=25)
+    ap.add_argument("--cheap", type=int, default=100_000, help="LinEx/LW/UD/ZI bettors")
     ap.add_argument("--out", default="gpurun_out/bettors.json")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
     res = run(args.bettors, args.d_lo, args.d_hi, args.every, args.max_rounds,
-              judge_every=args.judge_every, log=lambda m: print(f"[bettors] {m}", flush=True))
+              judge_every=args.judge_every, n_cheap=args.cheap, log=lambda m: print(f"[bettors] {m}", flush=True))
     res["wall_s"] = time.perf_counter() - t0
     print(json.dumps(res), flush=True)
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)

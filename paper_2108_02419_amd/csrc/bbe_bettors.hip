@@ -149,3 +149,18 @@ BBE_API int bbe_bettor_views(const bbe_bettors* b, const float* trace, uint32_t 
     if (e != hipSuccess) return hip_fail(e, "launching bettor_views_kernel");
     return ok();
 }
+
+BBE_API int bbe_rp_views(const uint64_t* wins, int n_bettors, int n, int row_stride,
+                         uint8_t* views, uint32_t* counts, void* stream) {
+    if (!views && !counts) return fail(BBE_EINVAL, "views and counts are both NULL");
+    if (n < 1 || n > BBE_MAX_COMPETITORS)
+        return fail(BBE_EINVAL, "n must be in 1..%d", BBE_MAX_COMPETITORS);
+    if (row_stride < n) return fail(BBE_EINVAL, "row_stride must be >= n");
+    if (n_bettors < 0) return fail(BBE_EINVAL, "n_bettors must be >= 0");
+    if (n_bettors > 0 && !wins) return fail(BBE_EINVAL, "wins is NULL");
+    hipError_t e = bbe::launch_rp_views(reinterpret_cast<const unsigned long long*>(wins),
+                                        (uint32_t)n_bettors, n, row_stride, views, counts,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching rp_views_kernel");
+    return ok();
+}

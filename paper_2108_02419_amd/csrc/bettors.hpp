@@ -50,8 +50,14 @@ struct ViewArgs {
 
 constexpr int kViewBlock = 256;
 constexpr int kViewRowsPerBlock = 8;
+// rows of history staged in LDS for LinEx windows (longer windows read the
+// trace in global memory)
+constexpr int kViewWindow = 120;
 
 hipError_t launch_race_trace(const TraceArgs& a, hipStream_t s);
 hipError_t launch_bettor_views(const ViewArgs& a, hipStream_t s);
+// RP(d) views from win counts [n_bettors][stride]; counts [n] cleared first.
+hipError_t launch_rp_views(const unsigned long long* wins, uint32_t n_bettors, int n, int stride,
+                           uint8_t* views, uint32_t* counts, hipStream_t s);
 
 }  // namespace bbe

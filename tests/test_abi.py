@@ -166,3 +166,12 @@ def test_bettors_reject_before_device_work(L):
         assert L.bbe_race_trace(race.handle, None, 1, 0, 0, rows, buf, buf, None) == _bbe.EINVAL
     assert L.bbe_race_trace(race.handle, None, 1, 0, 0, 10, None, buf, None) == _bbe.EINVAL
     assert L.bbe_race_trace(None, None, 1, 0, 0, 10, buf, buf, None) == _bbe.EINVAL
+
+
+def test_rp_views_reject_before_device_work(L):
+    buf = ctypes.c_void_p(16)  # never dereferenced
+    for n, stride in ((0, 20), (21, 21), (5, 4)):
+        assert L.bbe_rp_views(buf, 10, n, stride, buf, buf, None) == _bbe.EINVAL
+    assert L.bbe_rp_views(buf, -1, 5, 20, buf, buf, None) == _bbe.EINVAL
+    assert L.bbe_rp_views(None, 10, 5, 20, buf, buf, None) == _bbe.EINVAL
+    assert L.bbe_rp_views(buf, 10, 5, 20, None, None, None) == _bbe.EINVAL

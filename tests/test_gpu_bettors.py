@@ -142,3 +142,18 @@ def test_views_full_size_sampled(torch, orc):
     for r in range(0, tr.shape[0], 7):
         np.testing.assert_array_equal(np.bincount(v[r], minlength=20), c[r])
     assert (c.sum(axis=1) == kinds.size).all()
+
+
+@pytest.mark.parametrize("nb,n,stride", [(1, 1, 20), (300, 20, 20), (1000, 7, 20), (513, 5, 5),
+                                         (0, 4, 20)])
+def test_rp_views_match_oracle(torch, nb, n, stride):
+    rng = np.random.default_rng(nb + n)
+    wins = rng.integers(0, 4, (nb, stride)).astype(np.int64)  # small counts: many ties
+    if nb:
+        wins[: nb // 10, :] = 0  # bettors with no recorded win
+    announce(f"rp views bettors={nb} n={n} stride={stride}")
+    views, counts = api.rp_views(_dev(torch, wins), n)
+    torch.cuda.synchronize()
+    want_v, want_c = OB.rp_views(wins.astype(np.uint64), n)
+    np.testing.assert_array_equal(views.cpu().numpy(), want_v)
+    np.testing.assert_array_equal(counts.cpu().numpy().astype(np.uint32), want_c)
