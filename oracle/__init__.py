@@ -18,7 +18,9 @@ Contents
 ``bettors.py``     the cheap in-play bettor rules (LinEx, LW, UD, ZI).
 
 Functions here take and return numpy arrays.  Competitor parameters are an
-``[n, 5]`` float32 array of ``(lo, hi, pref, rho, theta)`` rows.
+``[n, 5]`` float32 array of ``(lo, hi, pref, rho, theta)`` rows, or ``[n, 7]``
+with the time term ``(gamma, tau)`` of the responsiveness appended
+(``[n, 5]`` means gamma = 0).
 """
 from __future__ import annotations
 
@@ -85,6 +87,16 @@ def _f32(a):
     return None if a is None else np.ascontiguousarray(a, dtype=np.float32)
 
 
+def _comp(comp) -> np.ndarray:
+    """Competitor rows as the C oracle takes them: [n, 7] float32."""
+    c = np.asarray(comp, dtype=np.float32)
+    if c.ndim != 2 or c.shape[1] not in (5, 7):
+        raise OracleError("competitor rows must have 5 or 7 columns")
+    if c.shape[1] == 5:
+        c = np.concatenate([c, np.zeros((c.shape[0], 2), np.float32)], axis=1)
+    return np.ascontiguousarray(c)
+
+
 class OracleError(ValueError):
     pass
 
@@ -106,7 +118,7 @@ def race_sim(comp, L, n_sims, seed, request=0, state=None, sim_begin=0, stop_aft
     Returns ``(orders [n_sims, n] uint8 or None, wins [n] uint64,
     competitor_steps int)``.
     """
-    comp = _f32(comp)
+    comp = _comp(comp)
     n = comp.shape[0]
     if stop_after is None:
         stop_after = n
@@ -130,7 +142,7 @@ def race_draws(comp, L, draws, state=None, stop_after=None, return_used=False,
 
     Returns the orders, plus (on request) the consumed-draw mask and the
     positions after every tick (``[seq, tick, n]``, NaN past the end)."""
-    comp = _f32(comp)
+    comp = _comp(comp)
     n = comp.shape[0]
     if stop_after is None:
         stop_after = n
@@ -159,7 +171,7 @@ def race_draws(comp, L, draws, state=None, stop_after=None, return_used=False,
 def race_prefix(comp, L, seed, request, sim, target, state=None):
     """Advance one simulated race until the leader is at ``target``; returns
     the in-play state ``(tick, pos, prev)``."""
-    comp = _f32(comp)
+    comp = _comp(comp)
     n = comp.shape[0]
     t0, pos, prev = 0, None, None
     if state is not None:
@@ -179,7 +191,7 @@ def race_trace(comp, L, seed, request, sim, max_rows, state=None):
     """Positions ``[rows, n]`` of one simulated race tick by tick, from the
     state (row 0) until just before the first tick in which a competitor
     would reach the line, or ``max_rows`` rows."""
-    comp = _f32(comp)
+    comp = _comp(comp)
     n = comp.shape[0]
     t0, pos, prev = 0, None, None
     if state is not None:

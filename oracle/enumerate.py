@@ -15,7 +15,8 @@ the same draws and must reproduce the same order.
 
 Single-precision operation order (one rounding per operation):
   elo = P*lo, espan = P*(hi-lo), alpha = 1-rho, beta = (2*rho)/L  (set-up)
-  R = alpha + beta*d_c;  unblocked: S = R*(elo + espan*u);
+  R = (alpha + beta*d_c) + gamma*min(t, tau)  (t the absolute tick; rows of
+      5 parameters mean gamma = 0);  unblocked: S = R*(elo + espan*u);
   blocked: S = R*min(s_c, s_ahead);  crossing fraction (L - d_old)/S.
 """
 from __future__ import annotations
@@ -34,8 +35,12 @@ class Race:
         self.n = comp.shape[0]
         self.L = f32(L)
         self.elo, self.espan, self.alpha, self.beta, self.theta = [], [], [], [], []
-        for lo, hi, pref, rho, theta in comp:
-            lo, hi, pref, rho, theta = f32(lo), f32(hi), f32(pref), f32(rho), f32(theta)
+        self.gamma, self.tau = [], []
+        for row in comp:
+            lo, hi, pref, rho, theta = (f32(v) for v in row[:5])
+            gamma, tau = (f32(row[5]), f32(row[6])) if len(row) == 7 else (f32(0), f32(0))
+            self.gamma.append(gamma)
+            self.tau.append(tau)
             self.elo.append(f32(pref * lo))
             self.espan.append(f32(pref * f32(hi - lo)))
             self.alpha.append(f32(f32(1.0) - rho))
@@ -66,6 +71,7 @@ def enumerate_race(comp, L, K, stop_after=None, state=None, max_ticks=64):
     race = Race(comp, L)
     n = race.n
     stop_after = n if stop_after is None else stop_after
+    t0 = 0 if state is None else int(state[0])
     if state is None:
         d0 = [f32(0.0)] * n
         s0 = [f32(0.0)] * n
@@ -88,7 +94,8 @@ def enumerate_race(comp, L, K, stop_after=None, state=None, max_ticks=64):
         plan = {}
         for c in sorted(running):
             gap, s_ahead = _ahead(race, d, s, running, c)
-            R = f32(race.alpha[c] + f32(race.beta[c] * d[c]))
+            th = min(f32(t0 + tick), race.tau[c])
+            R = f32(f32(race.alpha[c] + f32(race.beta[c] * d[c])) + f32(race.gamma[c] * th))
             if gap > race.theta[c]:
                 plan[c] = ("free", R, None)
             else:

@@ -30,7 +30,11 @@
  *   elo + espan*u with elo = fl(P*lo), espan = fl(P*fl(hi-lo)).
  *   R_c(d) = 1 + rho_c*(2 d_c/L - 1) = alpha_c + beta_c*d_c with
  *   alpha_c = fl(1-rho_c), beta_c = fl(2 rho_c / L), evaluated on the
- *   competitor's own start-of-tick position.
+ *   competitor's own start-of-tick position; R_c may also depend on time
+ *   (Section 3 writes R_c(t, d)): R = fl(fl(alpha + fl(beta*d)) +
+ *   fl(gamma*th)) with th = min(t, tau) for the absolute tick t, so the
+ *   pace drifts by gamma per tick until tick tau and then holds.  gamma = 0
+ *   (the default) adds +0 and leaves R unchanged.
  *   The nearest competitor ahead is the running competitor i != c with the
  *   smallest position d_i > d_c, the lowest index among equal positions;
  *   the gap is fl(d_i - d_c).  Nobody ahead means an infinite gap.
@@ -117,9 +121,11 @@ typedef struct {
     float elo[ORC_MAX_N], espan[ORC_MAX_N];
     float alpha[ORC_MAX_N], beta[ORC_MAX_N];
     float theta[ORC_MAX_N];
+    float gamma[ORC_MAX_N], tau[ORC_MAX_N];
 } orc_race;
 
-/* comp is [n][5] = {lo, hi, pref, rho, theta} per competitor. */
+/* comp is [n][7] = {lo, hi, pref, rho, theta, gamma, tau} per competitor;
+ * gamma and tau give R_c its dependence on time (below).                */
 static int race_setup(int n, float L, const float *comp, orc_race *r)
 {
     if (n < 1 || n > ORC_MAX_N) return ORC_EINVAL;
@@ -128,11 +134,13 @@ static int race_setup(int n, float L, const float *comp, orc_race *r)
     r->n = n;
     r->L = L;
     for (int c = 0; c < n; ++c) {
-        float lo = comp[5 * c + 0], hi = comp[5 * c + 1];
-        float pref = comp[5 * c + 2], rho = comp[5 * c + 3], theta = comp[5 * c + 4];
+        const float *q = comp + 7 * c;
+        float lo = q[0], hi = q[1], pref = q[2], rho = q[3], theta = q[4];
+        float gamma = q[5], tau = q[6];
         if (!isfinite(lo) || !isfinite(hi) || !isfinite(pref) || !isfinite(rho) ||
-            !isfinite(theta))
+            !isfinite(theta) || !isfinite(gamma) || !isfinite(tau))
             return ORC_EINVAL;
+        if (!(tau >= 0.0f) || tau > 16777216.0f || tau != floorf(tau)) return ORC_EINVAL;
         if (!(lo > 0.0f) || !(hi >= lo)) return ORC_EINVAL;
         if (!(pref > 0.0f) || !(pref <= 1.0f)) return ORC_EINVAL;
         if (!(fabsf(rho) < 1.0f)) return ORC_EINVAL;
@@ -143,8 +151,15 @@ static int race_setup(int n, float L, const float *comp, orc_race *r)
         r->alpha[c] = 1.0f - rho;
         r->beta[c] = (2.0f * rho) / L;
         r->theta[c] = theta;
-        /* S > 0 keeps the race finite; bound how long it can take. */
-        double min_step = (double)r->elo[c] * (1.0 - fabs((double)rho));
+        r->gamma[c] = gamma;
+        r->tau[c] = tau;
+        /* S > 0 keeps the race finite: R is at least 1 - |rho| + min(0,
+         * gamma*tau) over d in [0, L) and all t; a slowing time term must
+         * leave it at least 2^-10.  Bound how long the race can take.     */
+        double slow = (double)gamma * (double)tau;
+        double r_min = 1.0 - fabs((double)rho) + (slow < 0.0 ? slow : 0.0);
+        if (slow < 0.0 && !(r_min >= 0x1p-10)) return ORC_EINVAL;
+        double min_step = (double)r->elo[c] * r_min;
         if (!(min_step > 0.0) || (double)L / min_step > ORC_EXPECTED_TICK_BOUND)
             return ORC_EINVAL;
     }
@@ -184,7 +199,10 @@ static void tick_steps(const orc_race *r, const float *d, const float *s, const 
         }
         float gap = ahead >= 0 ? d[ahead] - d[c] : INFINITY;
         float s_ahead = ahead >= 0 ? s[ahead] : 0.0f;
-        float R = r->alpha[c] + r->beta[c] * d[c];
+        /* R_c(t, d) = alpha + beta*d_c + gamma*min(t, tau): the own-position
+         * term, plus a time term frozen after tick tau (zero when gamma = 0) */
+        float th = fminf((float)t, r->tau[c]);
+        float R = (r->alpha[c] + r->beta[c] * d[c]) + r->gamma[c] * th;
         if (gap > r->theta[c]) {
             float u;
             if (draws) {

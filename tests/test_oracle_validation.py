@@ -23,6 +23,36 @@ def test_bad_competitors_rejected(orc, comp):
         orc.race_sim(comp, 2000.0, 10, 1)
 
 
+GOOD7 = np.array([[5.0, 8.0, 1.0, 0.1, 2.0, 0.001, 300.0]] * 3, np.float32)
+
+
+def _bad_pace(col, val):
+    c = GOOD7.copy()
+    c[1, col] = val
+    return c
+
+
+@pytest.mark.parametrize("comp", [
+    _bad_pace(5, np.nan), _bad_pace(5, np.inf), _bad_pace(6, -1.0), _bad_pace(6, 2.5),
+    _bad_pace(6, 2.0**25), _bad_pace(6, np.nan),
+    _bad_pace(5, -0.003),  # 1 - 0.1 - 0.9 = 0: the time term would stop the competitor
+])
+def test_bad_time_terms_rejected(orc, comp):
+    with pytest.raises(orc.OracleError):
+        orc.race_sim(comp, 2000.0, 10, 1)
+
+
+def test_time_term_accepted_and_zero_is_the_plain_race(orc):
+    ok = _bad_pace(5, -0.0029)  # R stays >= 1 - 0.1 - 0.87 = 0.03
+    orc.race_sim(ok, 2000.0, 10, 1)
+    plain = orc.race_sim(GOOD, 2000.0, 300, 4)
+    zero = GOOD7.copy()
+    zero[:, 5] = 0.0
+    same = orc.race_sim(zero, 2000.0, 300, 4)
+    for a, b in zip(plain, same):
+        np.testing.assert_array_equal(a, b)
+
+
 @pytest.mark.parametrize("kw", [
     dict(L=0.0), dict(L=-5.0), dict(L=np.inf), dict(n_sims=0), dict(stop_after=0),
     dict(stop_after=4), dict(sim_begin=2**32 - 5, n_sims=10),
