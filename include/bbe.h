@@ -83,6 +83,21 @@ typedef struct bbe_state {
  * Errors: BBE_EINVAL, BBE_ENOMEM.                                          */
 int bbe_race_init(const bbe_competitor *comp, int n, float track_len, bbe_race **out);
 
+/* Gives the competitors' responsiveness a time term (paper Section 3: R_c
+ * depends on time as well as on the positions, to model a competitor that
+ * starts fast and fades, or starts slow and finishes strongly):
+ *   R_c(t, d) = fl(fl(alpha_c + fl(beta_c * d_c)) + fl(gamma_c * th)),
+ *   th = min(t, tau_c),
+ * with t the absolute tick (the state's tick counts from the start of the
+ * race), so the pace drifts by gamma_c per tick until tick tau_c and then
+ * holds.  Host arrays gamma, tau float[n]: gamma finite; tau an integer in
+ * 0..2^24; a slowing term must keep 1 - |rho_c| + gamma_c*tau_c >= 2^-10,
+ * and the race must still end within BBE_EXPECTED_TICK_BOUND ticks at its
+ * slowest.  All zeros (the state after bbe_race_init) is the plain race;
+ * races with some gamma != 0 run kernels that evaluate the term.
+ * Errors: BBE_EINVAL (the race is left unchanged).                         */
+int bbe_race_set_pace(bbe_race *race, const float *gamma, const float *tau);
+
 /* Release a race handle (NULL is ignored). */
 void bbe_race_free(bbe_race *race);
 

@@ -54,6 +54,7 @@ SIGNATURES = {
     "bbe_race_init": (_I, [_P, _I, _F, _P]),
     "bbe_race_free": (None, [_P]),
     "bbe_race_n": (_I, [_P]),
+    "bbe_race_set_pace": (_I, [_P, _P, _P]),
     "bbe_race_sim": (_I, [_P, _P, _U32, _U32, _U64, _U32, _I, _P, _P, _P, _P]),
     "bbe_win_probs": (_I, [_P, _I, _I, _I, _P, _P]),
     "bbe_race_prefix": (_I, [_P, _P, _U64, _U32, _U32, _F, _P, _P, _P, _P]),
@@ -116,21 +117,26 @@ def _dptr(t):
 
 
 class Race:
-    """A validated race: n competitors (rows lo, hi, pref, rho, theta) on a
-    track of length ``track_len``."""
+    """A validated race: n competitors (rows lo, hi, pref, rho, theta, and
+    optionally the time term gamma, tau of the responsiveness) on a track of
+    length ``track_len``."""
 
     def __init__(self, comp, track_len: float):
-        comp = np.ascontiguousarray(comp, dtype=np.float32)
-        if comp.ndim != 2 or comp.shape[1] != 5:
-            raise BBEError(EINVAL, "comp must be [n, 5]")
+        comp = np.asarray(comp, dtype=np.float32)
+        if comp.ndim != 2 or comp.shape[1] not in (5, 7):
+            raise BBEError(EINVAL, "comp must be [n, 5] or [n, 7]")
         self.n = int(comp.shape[0])
-        self.comp = comp
+        self.comp = np.ascontiguousarray(comp[:, :5])
+        self.pace = (np.ascontiguousarray(comp[:, 5]), np.ascontiguousarray(comp[:, 6])) \
+            if comp.shape[1] == 7 else None
         self.track_len = float(track_len)
         # rows of 5 float32 are bbe_competitor structs
         h = ctypes.c_void_p()
-        _check(lib().bbe_race_init(comp.ctypes.data if self.n else None, self.n, self.track_len,
-                                   ctypes.byref(h)))
+        _check(lib().bbe_race_init(self.comp.ctypes.data if self.n else None, self.n,
+                                   self.track_len, ctypes.byref(h)))
         self._h = h
+        if self.pace is not None:
+            _check(lib().bbe_race_set_pace(h, self.pace[0].ctypes.data, self.pace[1].ctypes.data))
 
     @property
     def handle(self):

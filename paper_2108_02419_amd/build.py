@@ -6,6 +6,7 @@ no fast-math; packed-FP32 instructions are disabled.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import os
 import shutil
 import subprocess
@@ -16,7 +17,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbbe.so")
-SOURCES = ["race_kernels.hip", "batch_kernels.hip", "mlp_kernels.hip", "order_kernels.hip",
+SOURCES = ["race_kernels.hip", "race_kernels_paced.hip", "batch_kernels.hip",
+           "batch_kernels_paced.hip", "mlp_kernels.hip", "order_kernels.hip",
            "bettor_kernels.hip", "bbe_api.hip", "bbe_batch.hip", "bbe_mlp.hip",
            "bbe_bettors.hip"]
 ARCH = os.environ.get("BBE_OFFLOAD_ARCH", "gfx950")
@@ -38,16 +40,21 @@ def compile_flags() -> list[str]:
 
 def build(verbose: bool = False, extra: list[str] | None = None, out: str = LIB) -> str:
     """Compile every source and link ``libbbe.so`` (always recompiles)."""
-    objs = []
     build_dir = os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
+    objs = [os.path.join(build_dir, src.replace(".hip", ".o")) for src in SOURCES]
+
+    def compile_one(src, obj):
         cmd = [hipcc(), *compile_flags(), *(extra or []), "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
-        objs.append(obj)
+
+    # one compiler process per source, a few at a time
+    workers = max(1, min(len(SOURCES), os.cpu_count() or 1, 8))
+    with concurrent.futures.ThreadPoolExecutor(workers) as pool:
+        for f in [pool.submit(compile_one, s, o) for s, o in zip(SOURCES, objs)]:
+            f.result()
     tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     if verbose:

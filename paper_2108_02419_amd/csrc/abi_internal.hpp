@@ -18,6 +18,7 @@ struct bbe_race {
     float L;
     bbe_competitor comp[BBE_MAX_COMPETITORS];
     bbe::RaceConst rc;
+    bbe::RacePace pace;  // all zero unless bbe_race_set_pace
 };
 
 namespace bbe_abi {

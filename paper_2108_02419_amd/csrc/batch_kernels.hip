@@ -10,91 +10,15 @@
 // time with the request's parameters in its LDS records, and flushes the
 // item's wins with one 64-bit atomic per competitor.  Within a group, items
 // are ordered by expected length, longest first, so the shortest work ends
-// the queue.
+// the queue.  A group holding a race with a time term of R runs the paced
+// variant (which gives the same results on the group's other races).
+#include "batch_mc.hpp"
 #include "kernels.hpp"
 #include "race_sim.hpp"
 
 #include <utility>
 
 namespace bbe {
-
-// Per-wave LDS: draw table [kMaxN][64] floats, parameter records, win
-// histogram, and the request's start state in slot order (positions,
-// previous steps, competitor ids) so that it does not occupy registers.
-constexpr uint32_t kWaveU = kMaxN * 256;
-constexpr uint32_t kWavePar = kMaxN * 32;
-constexpr uint32_t kWaveHist = 128;
-constexpr uint32_t kWaveInit = kMaxN * 12;
-constexpr uint32_t kWaveBytes = kWaveU + kWavePar + kWaveHist + kWaveInit;
-
-__device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-template <int N>
-__device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, char* smem,
-                                          uint32_t wbase, int lane, uint32_t k0, uint32_t k1,
-                                          unsigned long long* wins_row,
-                                          unsigned long long& steps) {
-    const uint32_t ucol = wbase + lane * 4;
-    const uint32_t pbase = wbase + kWaveU;
-    uint32_t* hist = reinterpret_cast<uint32_t*>(smem + wbase + kWaveU + kWavePar);
-    float* d0 = reinterpret_cast<float*>(smem + wbase + kWaveU + kWavePar + kWaveHist);
-    float* s0 = d0 + kMaxN;
-    uint8_t* id0 = reinterpret_cast<uint8_t*>(s0 + kMaxN);
-    write_params<N>(smem, pbase, rq.rc, lane);
-    if (lane < N) {
-        hist[lane] = 0u;
-        d0[lane] = rq.d0[lane];
-        s0[lane] = rq.s0[lane];
-        id0[lane] = rq.id0[lane];
-    }
-    for (uint32_t g = 0; g < ch.count; g += 64) {
-        const bool live = g + lane < ch.count;
-        const uint32_t sim = rq.sim_begin + ch.first + g + lane;
-        // re-read the start state from LDS each generation rather than
-        // keeping 3N registers live across the loop
-        __asm__ volatile("" ::: "memory");
-        run_generation<N>(smem, ucol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim,
-                          rq.request, k0, k1, rq.stop_after, nullptr, hist, steps);
-    }
-    if (lane < N) {
-        uint32_t w = hist[lane];
-        if (w) atomicAdd(&wins_row[lane], (unsigned long long)w);
-    }
-}
-
-// Waves per SIMD the register allocation aims for: 4 where the body fits in
-// 128 VGPRs without spilling, else 3.
-template <int N>
-constexpr int batch_waves_per_eu() {
-    return 4;
-}
-
-// Persistent kernel for the work items of one competitor count; up to 4
-// waves per workgroup (blockDim.x = 64 * waves).
-template <int N>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<N>())))
-    batch_mc_kernel(const BatchArgs a) {
-    extern __shared__ __attribute__((aligned(16))) char smem[];  // waves * kWaveBytes
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const uint32_t wbase = wave * kWaveBytes;
-    unsigned long long steps = 0ull;
-    for (;;) {
-        uint32_t ci = 0;
-        if (lane == 0) ci = atomicAdd(a.queue, 1u);
-        ci = __builtin_amdgcn_readfirstlane(ci);
-        if (ci >= a.n_chunks) break;
-        const Chunk ch = a.chunks[ci];
-        run_chunk<N>(a.reqs[ch.req], ch, smem, wbase, lane, a.k0, a.k1,
-                     a.wins + (size_t)ch.req * kMaxN, steps);
-    }
-    steps = wave_sum_u64b(steps);
-    if (a.steps && lane == 0 && steps) atomicAdd(a.steps, steps);
-}
 
 __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, int n) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -131,7 +55,7 @@ __device__ void run_prefix_lane(const ReqDesc& rq, char* smem, uint32_t ucol, ui
     for (int c = 0; c < N; ++c) {
         float4* rec = reinterpret_cast<float4*>(smem + pbase + c * 32);
         rec[0] = make_float4(rq.rc.elo[c], rq.rc.espan16[c], rq.rc.alpha[c], rq.rc.beta[c]);
-        rec[1] = make_float4(rq.rc.theta[c], 0.0f, 0.0f, 0.0f);
+        rec[1] = make_float4(rq.rc.theta[c], rq.pace.gamma[c], rq.pace.tau[c], 0.0f);
     }
     Slots<N> sl;
     slots_reset<N>(sl, rq.d0, rq.s0, rq.id0, pbase);
@@ -144,7 +68,8 @@ __device__ void run_prefix_lane(const ReqDesc& rq, char* smem, uint32_t ucol, ui
             break;
         }
         uint32_t cross =
-            slots_tick<N>(sl, smem, ucol, pbase, rq.rc.L, t, rq.prefix_sim, rq.request, k0, k1);
+            slots_tick<N, true>(sl, smem, ucol, pbase, rq.rc.L, t, rq.prefix_sim, rq.request, k0,
+                                k1);
         t += 1;
         if (cross) {
             ok = false;
@@ -194,7 +119,7 @@ __global__ void __launch_bounds__(64) prefix_batch_kernel(const ReqDesc* __restr
 template <int N>
 static hipError_t launch_batch_n(const BatchArgs& a, int waves_per_block, int grid,
                                  hipStream_t s) {
-    hipLaunchKernelGGL(batch_mc_kernel<N>, dim3(grid), dim3(64 * waves_per_block),
+    hipLaunchKernelGGL((batch_mc_kernel<N, false>), dim3(grid), dim3(64 * waves_per_block),
                        waves_per_block * kWaveBytes, s, a);
     return hipGetLastError();
 }
@@ -202,7 +127,7 @@ static hipError_t launch_batch_n(const BatchArgs& a, int waves_per_block, int gr
 template <int N>
 static int batch_occupancy_n(int waves_per_block) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<N>,
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<N, false>,
                                                      64 * waves_per_block,
                                                      waves_per_block * kWaveBytes) != hipSuccess)
         nb = 1;
@@ -224,18 +149,20 @@ static int dispatch_batch_occ(int n, int w, std::integer_sequence<int, I...>) {
     return table[n - 1](w);
 }
 
-hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid,
+hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid, bool paced,
                            hipStream_t s) {
     if (n < 1 || n > kMaxN || (waves_per_block != 1 && waves_per_block != 2 &&
                                waves_per_block != 4))
         return hipErrorInvalidValue;
+    if (paced) return launch_batch_mc_paced(a, n, waves_per_block, grid, s);
     return dispatch_batch(n, a, waves_per_block, grid, s,
                           std::make_integer_sequence<int, kMaxN>{});
 }
 
-int batch_blocks_per_cu(int n, int waves_per_block) {
-    static int cache[kMaxN + 1][5] = {};
+int batch_blocks_per_cu(int n, int waves_per_block, bool paced) {
     if (n < 1 || n > kMaxN || waves_per_block < 1 || waves_per_block > 4) return 1;
+    if (paced) return batch_blocks_per_cu_paced(n, waves_per_block);
+    static int cache[kMaxN + 1][5] = {};
     int& c = cache[n][waves_per_block];
     if (!c) c = dispatch_batch_occ(n, waves_per_block, std::make_integer_sequence<int, kMaxN>{});
     return c;

@@ -1,0 +1,92 @@
+// batch_mc.hpp -- the persistent batch kernel template (see
+// batch_kernels.hip).  Its plain variant is instantiated in
+// batch_kernels.hip and its paced variant (time term of R) in
+// batch_kernels_paced.hip, each in a translation unit of its own so that
+// neither affects the other's code generation.
+#pragma once
+
+#include "kernels.hpp"
+#include "race_sim.hpp"
+
+namespace bbe {
+
+// Per-wave LDS: draw table [kMaxN][64] floats, parameter records, win
+// histogram, and the request's start state in slot order (positions,
+// previous steps, competitor ids) so that it does not occupy registers.
+constexpr uint32_t kWaveU = kMaxN * 256;
+constexpr uint32_t kWavePar = kMaxN * 32;
+constexpr uint32_t kWaveHist = 128;
+constexpr uint32_t kWaveInit = kMaxN * 12;
+constexpr uint32_t kWaveBytes = kWaveU + kWavePar + kWaveHist + kWaveInit;
+
+__device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int N, bool kPaced>
+__device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, char* smem,
+                                          uint32_t wbase, int lane, uint32_t k0, uint32_t k1,
+                                          unsigned long long* wins_row,
+                                          unsigned long long& steps) {
+    const uint32_t ucol = wbase + lane * 4;
+    const uint32_t pbase = wbase + kWaveU;
+    uint32_t* hist = reinterpret_cast<uint32_t*>(smem + wbase + kWaveU + kWavePar);
+    float* d0 = reinterpret_cast<float*>(smem + wbase + kWaveU + kWavePar + kWaveHist);
+    float* s0 = d0 + kMaxN;
+    uint8_t* id0 = reinterpret_cast<uint8_t*>(s0 + kMaxN);
+    write_params<N>(smem, pbase, rq.rc, lane);
+    if constexpr (kPaced) write_pace<N>(smem, pbase, rq.pace, lane);
+    if (lane < N) {
+        hist[lane] = 0u;
+        d0[lane] = rq.d0[lane];
+        s0[lane] = rq.s0[lane];
+        id0[lane] = rq.id0[lane];
+    }
+    for (uint32_t g = 0; g < ch.count; g += 64) {
+        const bool live = g + lane < ch.count;
+        const uint32_t sim = rq.sim_begin + ch.first + g + lane;
+        // re-read the start state from LDS each generation rather than
+        // keeping 3N registers live across the loop
+        __asm__ volatile("" ::: "memory");
+        run_generation<N, kPaced>(smem, ucol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim,
+                          rq.request, k0, k1, rq.stop_after, nullptr, hist, steps);
+    }
+    if (lane < N) {
+        uint32_t w = hist[lane];
+        if (w) atomicAdd(&wins_row[lane], (unsigned long long)w);
+    }
+}
+
+// Waves per SIMD the register allocation aims for: 4 where the body fits in
+// 128 VGPRs without spilling, else 3.
+template <int N, bool kPaced = false>
+constexpr int batch_waves_per_eu() {
+    return (kPaced && N >= 16) ? 3 : 4;
+}
+
+// Persistent kernel for the work items of one competitor count; up to 4
+// waves per workgroup (blockDim.x = 64 * waves).
+template <int N, bool kPaced>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<N, kPaced>())))
+    batch_mc_kernel(const BatchArgs a) {
+    extern __shared__ __attribute__((aligned(16))) char smem[];  // waves * kWaveBytes
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t wbase = wave * kWaveBytes;
+    unsigned long long steps = 0ull;
+    for (;;) {
+        uint32_t ci = 0;
+        if (lane == 0) ci = atomicAdd(a.queue, 1u);
+        ci = __builtin_amdgcn_readfirstlane(ci);
+        if (ci >= a.n_chunks) break;
+        const Chunk ch = a.chunks[ci];
+        run_chunk<N, kPaced>(a.reqs[ch.req], ch, smem, wbase, lane, a.k0, a.k1,
+                     a.wins + (size_t)ch.req * kMaxN, steps);
+    }
+    steps = wave_sum_u64b(steps);
+    if (a.steps && lane == 0 && steps) atomicAdd(a.steps, steps);
+}
+
+}  // namespace bbe

@@ -38,6 +38,34 @@ BBE_API int bbe_race_init(const bbe_competitor* comp, int n, float track_len, bb
     return ok();
 }
 
+BBE_API int bbe_race_set_pace(bbe_race* race, const float* gamma, const float* tau) {
+    if (!race) return fail(BBE_EINVAL, "race is NULL");
+    if (!gamma || !tau) return fail(BBE_EINVAL, "NULL argument");
+    for (int c = 0; c < race->n; ++c) {
+        if (!std::isfinite(gamma[c])) return fail(BBE_EINVAL, "competitor %d: gamma not finite", c);
+        if (!(tau[c] >= 0.0f && tau[c] <= 16777216.0f) || tau[c] != std::floor(tau[c]))
+            return fail(BBE_EINVAL, "competitor %d: tau must be an integer in 0..2^24", c);
+        const double slow = (double)gamma[c] * (double)tau[c];
+        const double r_min = 1.0 - std::fabs((double)race->comp[c].rho) + (slow < 0.0 ? slow : 0.0);
+        if (slow < 0.0 && !(r_min >= 0x1p-10))
+            return fail(BBE_EINVAL, "competitor %d: the time term takes R below 2^-10", c);
+        const double slowest = (double)race->rc.elo[c] * r_min;
+        if (!(slowest > 0.0) || (double)race->L / slowest > (double)BBE_EXPECTED_TICK_BOUND)
+            return fail(BBE_EINVAL,
+                        "competitor %d: slowest free step %.3g needs more than %d ticks to "
+                        "cover the track",
+                        c, slowest, BBE_EXPECTED_TICK_BOUND);
+    }
+    int paced = 0;
+    for (int c = 0; c < race->n; ++c) {
+        race->pace.gamma[c] = gamma[c];
+        race->pace.tau[c] = tau[c];
+        if (gamma[c] != 0.0f) paced = 1;
+    }
+    race->pace.paced = paced;
+    return ok();
+}
+
 BBE_API void bbe_race_free(bbe_race* race) { delete race; }
 
 BBE_API int bbe_race_n(const bbe_race* race) {
@@ -58,6 +86,7 @@ BBE_API int bbe_race_sim(const bbe_race* race, const bbe_state* state, uint32_t 
     bbe::SimArgs a;
     std::memset(&a, 0, sizeof a);
     a.rc = race->rc;
+    a.pace = race->pace;
     int rc = check_state(race, state, a.d0, a.s0, a.id0, &a.t0);
     if (rc != BBE_OK) return rc;
     a.sim_begin = sim_begin;
@@ -79,7 +108,7 @@ BBE_API int bbe_race_sim(const bbe_race* race, const bbe_state* state, uint32_t 
 
     const int block = bbe::mc_block_size();
     uint64_t need = ((uint64_t)n_sims + block - 1) / block;
-    uint64_t resident = (uint64_t)bbe::mc_blocks_per_cu(race->n) * device_cus();
+    uint64_t resident = (uint64_t)bbe::mc_blocks_per_cu(race->n, race->pace.paced != 0) * device_cus();
     int grid = (int)(need < resident ? need : resident);
     if ((e = bbe::launch_race_mc(a, grid, s)) != hipSuccess)
         return hip_fail(e, "launching race_mc_kernel");
@@ -136,6 +165,7 @@ BBE_API int bbe_race_prefix(const bbe_race* race, const bbe_state* state, uint64
     bbe::PrefixArgs a;
     std::memset(&a, 0, sizeof a);
     a.rc = race->rc;
+    a.pace = race->pace;
     int rc = check_state(race, state, a.d0, a.s0, a.id0, &a.t0);
     if (rc != BBE_OK) return rc;
     a.request = request;
@@ -162,6 +192,7 @@ BBE_API int bbe_race_advance(const bbe_race* race, const bbe_state* state, uint6
     bbe::PrefixArgs a;
     std::memset(&a, 0, sizeof a);
     a.rc = race->rc;
+    a.pace = race->pace;
     int rc = check_state(race, state, a.d0, a.s0, a.id0, &a.t0);
     if (rc != BBE_OK) return rc;
     a.request = request;

@@ -26,6 +26,7 @@ struct Group {
     int n;           // competitor count of every item in the group
     uint32_t first;  // its items: chunks[first .. first + count)
     uint32_t count;
+    bool paced;      // some item's race has a time term of R
 };
 
 struct Work {
@@ -75,8 +76,9 @@ Work build_work(const std::vector<bbe::ReqDesc>& reqs, int sims_per_item) {
     for (auto& it : items) {
         const int n = (int)it.second.n;
         if (w.groups.empty() || w.groups.back().n != n)
-            w.groups.push_back({n, (uint32_t)w.chunks.size(), 0u});
+            w.groups.push_back({n, (uint32_t)w.chunks.size(), 0u, false});
         w.groups.back().count += 1;
+        if (reqs[it.second.req].pace.paced) w.groups.back().paced = true;
         w.chunks.push_back(it.second);
     }
     return w;
@@ -133,8 +135,8 @@ hipError_t enqueue(bbe_batch_plan* p, hipStream_t s) {
         a.steps = p->steps;
         a.k0 = p->k0;
         a.k1 = p->k1;
-        if ((e = bbe::launch_batch_mc(a, gr.n, p->shape.waves_per_block, p->grids[g], s)) !=
-            hipSuccess)
+        if ((e = bbe::launch_batch_mc(a, gr.n, p->shape.waves_per_block, p->grids[g], gr.paced,
+                                      s)) != hipSuccess)
             return e;
     }
     if (p->probs &&
@@ -163,7 +165,7 @@ int upload_work(bbe_batch_plan* p, const Shape& sh) {
     const int cus = device_cus();
     for (const Group& g : w.groups) {
         // resident capacity, but no more waves than the group has items
-        long cap = (long)bbe::batch_blocks_per_cu(g.n, sh.waves_per_block) * cus;
+        long cap = (long)bbe::batch_blocks_per_cu(g.n, sh.waves_per_block, g.paced) * cus;
         long need = ((long)g.count + sh.waves_per_block - 1) / sh.waves_per_block;
         p->grids.push_back((int)std::max(1L, std::min(cap, need)));
     }
@@ -186,6 +188,7 @@ int fill_desc(const bbe_request& q, int idx, bbe::ReqDesc& d) {
     if (!q.race) return fail(BBE_EINVAL, "request %d: race is NULL", idx);
     std::memset(&d, 0, sizeof d);
     d.rc = q.race->rc;
+    d.pace = q.race->pace;
     int rc = check_state(q.race, q.state, d.d0, d.s0, d.id0, &d.t0);
     if (rc != BBE_OK) return fail(rc, "request %d: %s", idx, g_err.c_str());
     d.request = q.request;

@@ -35,6 +35,7 @@ BBE_API int bbe_race_trace(const bbe_race* race, const bbe_state* state, uint64_
     bbe::TraceArgs a;
     std::memset(&a, 0, sizeof a);
     a.rc = race->rc;
+    a.pace = race->pace;
     int rc = check_state(race, state, a.d0, a.s0, a.id0, &a.t0);
     if (rc != BBE_OK) return rc;
     a.request = request;

@@ -46,6 +46,7 @@ __global__ void __launch_bounds__(64) race_trace_kernel(const TraceArgs a) {
     const int lane = threadIdx.x;
     const uint32_t ucol = lane * 4;
     write_params<N>(smem, kPar, a.rc, lane);
+    write_pace<N>(smem, kPar, a.pace, lane);
     __syncthreads();
     if (lane != 0) return;
     Slots<N> sl;
@@ -56,7 +57,7 @@ __global__ void __launch_bounds__(64) race_trace_kernel(const TraceArgs a) {
     // at most max_rows - 1 <= 2^20 ticks
     while (rows < a.max_rows) {
         const uint32_t cross =
-            slots_tick<N>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
+            slots_tick<N, true>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
         if (cross) break;
         t += 1;
         slots_restore<N>(sl);

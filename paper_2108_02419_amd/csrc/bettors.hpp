@@ -24,6 +24,7 @@ struct TraceArgs {
     uint32_t max_rows;
     float* trace;       // [max_rows][n]
     uint32_t* rows_out;  // [1]
+    RacePace pace;
 };
 
 // Bettor kinds, as numbered in the C ABI.

@@ -26,6 +26,7 @@ struct SimArgs {
     uint8_t* orders;            // [n_sims][n] or null
     unsigned long long* wins;   // [n], zeroed before launch, or null
     unsigned long long* steps;  // [1], zeroed before launch, or null
+    RacePace pace;
 };
 
 struct PrefixArgs {
@@ -42,10 +43,14 @@ struct PrefixArgs {
     uint32_t* tick_out;
     float* pos_out;
     float* prev_out;
+    RacePace pace;
 };
 
 int mc_block_size();
-int mc_blocks_per_cu(int n);
+int mc_blocks_per_cu(int n, bool paced);
+// the paced variants (race_kernels_paced.hip), used by the two above
+int mc_blocks_per_cu_paced(int n);
+hipError_t launch_race_mc_paced(const SimArgs& a, int grid, hipStream_t s);
 hipError_t launch_race_mc(const SimArgs& a, int grid, hipStream_t s);
 hipError_t launch_race_prefix(const PrefixArgs& a, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long* p, int n, hipStream_t s);
@@ -78,6 +83,7 @@ struct alignas(16) ReqDesc {
     // in-play state generation only: simulation index and leader target
     uint32_t prefix_sim;
     float target;
+    RacePace pace;
 };
 
 // A work item of the persistent kernel: simulations [first, first + count)
@@ -101,9 +107,14 @@ struct BatchArgs {
     uint32_t k0, k1;
 };
 
-hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid,
+// paced: the group holds a race with a time term of R (some gamma != 0)
+hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid, bool paced,
                            hipStream_t s);
-int batch_blocks_per_cu(int n, int waves_per_block);
+int batch_blocks_per_cu(int n, int waves_per_block, bool paced);
+// the paced variants (batch_kernels_paced.hip), used by the two above
+hipError_t launch_batch_mc_paced(const BatchArgs& a, int n, int waves_per_block, int grid,
+                                 hipStream_t s);
+int batch_blocks_per_cu_paced(int n, int waves_per_block);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
 hipError_t launch_batch_probs(const unsigned long long* wins, const ReqDesc* reqs, int n_reqs,
                               double* probs, hipStream_t s);

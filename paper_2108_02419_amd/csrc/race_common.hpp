@@ -33,6 +33,16 @@ struct RaceConst {
     float theta[kMaxN];
 };
 
+// Time term of R (R += fl(gamma * min(t, tau)) on the absolute tick t);
+// `paced` is set when some gamma != 0 and selects the kernels that evaluate
+// it.  Kept apart from RaceConst, at the end of the argument blocks, so the
+// plain kernels see the same argument layout as without it.
+struct RacePace {
+    float gamma[kMaxN];
+    float tau[kMaxN];
+    int paced;
+};
+
 // Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round forms the
 // 64-bit products of the two even counter words with the round multipliers
 // (one v_mad_u64_u32 each); the high halves are xored with the odd words

@@ -8,93 +8,15 @@
 // are counted in an LDS histogram (one LDS atomic per finished simulation)
 // and flushed with one 64-bit global atomic per competitor per workgroup;
 // competitor-steps are summed per simulation from the finishing ticks and
-// reduced per wave and per workgroup the same way.
+// reduced per wave and per workgroup the same way.  kPaced selects the
+// variant that evaluates the time term of R (races with some gamma != 0).
 #include "kernels.hpp"
+#include "race_mc.hpp"
 #include "race_sim.hpp"
 
 #include <utility>
 
 namespace bbe {
-
-constexpr int kWaves = 4;
-constexpr int kBlock = 64 * kWaves;
-
-template <int N>
-struct BlockLds {
-    static constexpr uint32_t kU = 0;                                      // [wave] u tables
-    static constexpr uint32_t kPar = ((kWaves * N * 256 + 1023) / 1024) * 1024;  // records
-    static constexpr uint32_t kWins = kPar + 1024;                        // u32[N]
-    static constexpr uint32_t kSteps = kWins + 128;                        // u64
-    static constexpr uint32_t kInit = kSteps + 16;  // start state: d0, s0 (f32[N]), id0 (u8[N])
-    static constexpr uint32_t kBytes = kInit + kMaxN * 12;
-};
-
-__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
-// Waves per SIMD the register allocation aims for: 4 where the body fits in
-// 128 VGPRs without spilling, else 3.
-template <int N>
-constexpr int mc_waves_per_eu() {
-    return 4;
-}
-
-template <int N>
-__global__ void __launch_bounds__(kBlock)
-    __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<N>()))) race_mc_kernel(const SimArgs a) {
-    using Lay = BlockLds<N>;
-    __shared__ __attribute__((aligned(1024))) char smem[Lay::kBytes];
-    const int wave = threadIdx.x >> 6;
-    const int lane = threadIdx.x & 63;
-    const uint32_t ucol = Lay::kU + wave * (N * 256) + lane * 4;
-    // one record table for the workgroup (every wave simulates the same
-    // race), at a compile-time offset
-    const uint32_t pbase = Lay::kPar;
-    uint32_t* s_wins = reinterpret_cast<uint32_t*>(smem + Lay::kWins);
-    unsigned long long* s_steps = reinterpret_cast<unsigned long long*>(smem + Lay::kSteps);
-
-    float* s_d0 = reinterpret_cast<float*>(smem + Lay::kInit);
-    float* s_s0 = s_d0 + kMaxN;
-    uint8_t* s_id0 = reinterpret_cast<uint8_t*>(s_s0 + kMaxN);
-    write_params<N>(smem, pbase, a.rc, (int)threadIdx.x);
-    if (threadIdx.x < N) {
-        s_wins[threadIdx.x] = 0u;
-        s_d0[threadIdx.x] = a.d0[threadIdx.x];
-        s_s0[threadIdx.x] = a.s0[threadIdx.x];
-        s_id0[threadIdx.x] = a.id0[threadIdx.x];
-    }
-    if (threadIdx.x == 0) *s_steps = 0ull;
-    __syncthreads();
-
-    const float L = a.rc.L;
-    const uint64_t wave_stride = (uint64_t)gridDim.x * kWaves * 64;
-    unsigned long long steps = 0ull;
-
-    for (uint64_t base = ((uint64_t)blockIdx.x * kWaves + wave) * 64; base < a.n_sims;
-         base += wave_stride) {
-        const uint64_t j = base + lane;
-        const bool live = j < a.n_sims;
-        uint8_t* row = (a.orders && live) ? a.orders + j * N : nullptr;
-        // re-read the start state from LDS each generation rather than
-        // keeping it live (in registers) across the loop
-        __asm__ volatile("" ::: "memory");
-        run_generation<N>(smem, ucol, pbase, L, s_d0, s_s0, s_id0, a.t0, live,
-                          a.sim_begin + (uint32_t)j, a.request, a.k0, a.k1, a.stop_after, row,
-                          s_wins, steps);
-    }
-
-    steps = wave_sum_u64(steps);
-    if (lane == 0) atomicAdd(s_steps, steps);
-    __syncthreads();
-    if (a.wins && threadIdx.x < N) {
-        uint32_t w = s_wins[threadIdx.x];
-        if (w) atomicAdd(&a.wins[threadIdx.x], (unsigned long long)w);
-    }
-    if (a.steps && threadIdx.x == 0) atomicAdd(a.steps, *s_steps);
-}
 
 // One lane advances one simulation until the leader reaches the target.
 template <int N>
@@ -104,6 +26,7 @@ __global__ void __launch_bounds__(64) race_prefix_kernel(const PrefixArgs a) {
     const int lane = threadIdx.x;
     const uint32_t ucol = lane * 4;
     write_params<N>(smem, kPar, a.rc, lane);
+    write_pace<N>(smem, kPar, a.pace, lane);
     __syncthreads();
     if (lane != 0) return;
     Slots<N> sl;
@@ -118,7 +41,7 @@ __global__ void __launch_bounds__(64) race_prefix_kernel(const PrefixArgs a) {
             break;
         }
         uint32_t cross =
-            slots_tick<N>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
+            slots_tick<N, true>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
         t += 1;
         if (cross) {
             ok = false;
@@ -150,14 +73,14 @@ __global__ void win_probs_kernel(const unsigned long long* __restrict__ wins, in
 
 template <int N>
 static hipError_t launch_mc_n(const SimArgs& a, int grid, hipStream_t s) {
-    hipLaunchKernelGGL(race_mc_kernel<N>, dim3(grid), dim3(kBlock), 0, s, a);
+    hipLaunchKernelGGL((race_mc_kernel<N, false>), dim3(grid), dim3(kBlock), 0, s, a);
     return hipGetLastError();
 }
 
 template <int N>
 static int occupancy_n() {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, race_mc_kernel<N>, kBlock, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, race_mc_kernel<N, false>, kBlock, 0) !=
         hipSuccess)
         nb = 1;
     return nb > 0 ? nb : 1;
@@ -196,13 +119,15 @@ using Seq = std::make_integer_sequence<int, kMaxN>;
 
 int mc_block_size() { return kBlock; }
 
-int mc_blocks_per_cu(int n) {
-    static int cache[kMaxN + 1] = {0};
+int mc_blocks_per_cu(int n, bool paced) {
+    if (paced) return mc_blocks_per_cu_paced(n);
+    static int cache[kMaxN + 1] = {};
     if (!cache[n]) cache[n] = dispatch_occ(n, Seq{});
     return cache[n];
 }
 
 hipError_t launch_race_mc(const SimArgs& a, int grid, hipStream_t s) {
+    if (a.pace.paced) return launch_race_mc_paced(a, grid, s);
     return dispatch_mc(a.rc.n, a, grid, s, Seq{});
 }
 

@@ -1,0 +1,94 @@
+// race_mc.hpp -- the Monte-Carlo kernel template (see race_kernels.hip).
+// Its plain variant is instantiated in race_kernels.hip and its paced
+// variant (time term of R) in race_kernels_paced.hip, each in a translation
+// unit of its own so that neither affects the other's code generation.
+#pragma once
+
+#include "kernels.hpp"
+#include "race_sim.hpp"
+
+namespace bbe {
+
+constexpr int kWaves = 4;
+constexpr int kBlock = 64 * kWaves;
+
+template <int N>
+struct BlockLds {
+    static constexpr uint32_t kU = 0;                                      // [wave] u tables
+    static constexpr uint32_t kPar = ((kWaves * N * 256 + 1023) / 1024) * 1024;  // records
+    static constexpr uint32_t kWins = kPar + 1024;                        // u32[N]
+    static constexpr uint32_t kSteps = kWins + 128;                        // u64
+    static constexpr uint32_t kInit = kSteps + 16;  // start state: d0, s0 (f32[N]), id0 (u8[N])
+    static constexpr uint32_t kBytes = kInit + kMaxN * 12;
+};
+
+__device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Waves per SIMD the register allocation aims for: 4 where the body fits in
+// 128 VGPRs without spilling, else 3 (the paced variant's larger competitor
+// counts, which hold two more prefetched parameters per slot).
+template <int N, bool kPaced = false>
+constexpr int mc_waves_per_eu() {
+    return (kPaced && N >= 16) ? 3 : 4;
+}
+
+template <int N, bool kPaced>
+__global__ void __launch_bounds__(kBlock)
+    __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<N, kPaced>()))) race_mc_kernel(const SimArgs a) {
+    using Lay = BlockLds<N>;
+    __shared__ __attribute__((aligned(1024))) char smem[Lay::kBytes];
+    const int wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const uint32_t ucol = Lay::kU + wave * (N * 256) + lane * 4;
+    // one record table for the workgroup (every wave simulates the same
+    // race), at a compile-time offset
+    const uint32_t pbase = Lay::kPar;
+    uint32_t* s_wins = reinterpret_cast<uint32_t*>(smem + Lay::kWins);
+    unsigned long long* s_steps = reinterpret_cast<unsigned long long*>(smem + Lay::kSteps);
+
+    float* s_d0 = reinterpret_cast<float*>(smem + Lay::kInit);
+    float* s_s0 = s_d0 + kMaxN;
+    uint8_t* s_id0 = reinterpret_cast<uint8_t*>(s_s0 + kMaxN);
+    write_params<N>(smem, pbase, a.rc, (int)threadIdx.x);
+    if constexpr (kPaced) write_pace<N>(smem, pbase, a.pace, (int)threadIdx.x);
+    if (threadIdx.x < N) {
+        s_wins[threadIdx.x] = 0u;
+        s_d0[threadIdx.x] = a.d0[threadIdx.x];
+        s_s0[threadIdx.x] = a.s0[threadIdx.x];
+        s_id0[threadIdx.x] = a.id0[threadIdx.x];
+    }
+    if (threadIdx.x == 0) *s_steps = 0ull;
+    __syncthreads();
+
+    const float L = a.rc.L;
+    const uint64_t wave_stride = (uint64_t)gridDim.x * kWaves * 64;
+    unsigned long long steps = 0ull;
+
+    for (uint64_t base = ((uint64_t)blockIdx.x * kWaves + wave) * 64; base < a.n_sims;
+         base += wave_stride) {
+        const uint64_t j = base + lane;
+        const bool live = j < a.n_sims;
+        uint8_t* row = (a.orders && live) ? a.orders + j * N : nullptr;
+        // re-read the start state from LDS each generation rather than
+        // keeping it live (in registers) across the loop
+        __asm__ volatile("" ::: "memory");
+        run_generation<N, kPaced>(smem, ucol, pbase, L, s_d0, s_s0, s_id0, a.t0, live,
+                          a.sim_begin + (uint32_t)j, a.request, a.k0, a.k1, a.stop_after, row,
+                          s_wins, steps);
+    }
+
+    steps = wave_sum_u64(steps);
+    if (lane == 0) atomicAdd(s_steps, steps);
+    __syncthreads();
+    if (a.wins && threadIdx.x < N) {
+        uint32_t w = s_wins[threadIdx.x];
+        if (w) atomicAdd(&a.wins[threadIdx.x], (unsigned long long)w);
+    }
+    if (a.steps && threadIdx.x == 0) atomicAdd(a.steps, *s_steps);
+}
+
+}  // namespace bbe

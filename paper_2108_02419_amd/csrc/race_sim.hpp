@@ -23,8 +23,9 @@
 //   2. competitor ahead: the running competitor with the smallest position
 //      greater than d_c (lowest index among equal positions); gap =
 //      fl(d_ahead - d_c), +inf if nobody is ahead;
-//   3. Eq. 1: R = alpha + beta*d; free: S = R*(elo + espan*u); blocked
-//      (gap <= theta): S = R*min(s_c, s_ahead);
+//   3. Eq. 1: R = alpha + beta*d (+ gamma*min(t, tau) in the paced
+//      variant); free: S = R*(elo + espan*u); blocked (gap <= theta):
+//      S = R*min(s_c, s_ahead);
 //   4. synchronous update d += S, s = S of the running competitors; a
 //      competitor whose new position reaches L crosses the line;
 //   5. this tick's finishers are ranked after the earlier ones, among
@@ -66,7 +67,8 @@ __device__ __forceinline__ float parked() {
 }
 
 // Writes the parameter records of a race into a record block: record c =
-// (elo, espan16, alpha, beta, theta, -, -, -) at pbase + 32*c.
+// (elo, espan16, alpha, beta, theta, gamma, tau, -) at pbase + 32*c; gamma
+// and tau are written (by the same lane, afterwards) by write_pace.
 template <int N>
 __device__ __forceinline__ void write_params(char* smem, uint32_t pbase, const RaceConst& rc,
                                             int lane) {
@@ -74,6 +76,16 @@ __device__ __forceinline__ void write_params(char* smem, uint32_t pbase, const R
         float4* rec = reinterpret_cast<float4*>(smem + pbase + lane * 32);
         rec[0] = make_float4(rc.elo[lane], rc.espan16[lane], rc.alpha[lane], rc.beta[lane]);
         rec[1] = make_float4(rc.theta[lane], 0.0f, 0.0f, 0.0f);
+    }
+}
+
+template <int N>
+__device__ __forceinline__ void write_pace(char* smem, uint32_t pbase, const RacePace& pc,
+                                          int lane) {
+    if (lane < N) {
+        float* rec = reinterpret_cast<float*>(smem + pbase + lane * 32);
+        rec[5] = pc.gamma[lane];
+        rec[6] = pc.tau[lane];
     }
 }
 
@@ -95,8 +107,9 @@ __device__ __forceinline__ void slots_reset(Slots<N>& sl, const float* __restric
 // of the draw table (competitor c's draw at ucol + 256*c), `pbase` that of
 // the parameter records.  Returns the bit mask of slots that crossed the
 // line (their position still holds the start-of-tick value; their s holds
-// the step S that took them over).
-template <int N>
+// the step S that took them over).  kPaced adds the time term of R (with
+// gamma = 0 it adds +0, so both variants agree on unpaced races).
+template <int N, bool kPaced = false>
 __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_t ucol,
                                                uint32_t pbase, float L, uint32_t t,
                                                uint32_t sim, uint32_t request, uint32_t k0,
@@ -124,14 +137,22 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
     //    and parameter record are read from LDS kPf slots ahead of use.
     const uint32_t ubias = ucol - 8u * pbase;
     constexpr int kPf = 4;
-    float pu[N], pth[N];
+    float pu[N], pth[N], pga[N], pta[N];
     float4 pp[N];
+    const float tf = (float)t;
 #pragma unroll
     for (int k = N - 1; k >= 0 && k >= N - kPf; --k) {
         const uint32_t rec = sl.rec[k];
         pu[k] = lds_f32(smem, ubias + (rec << 3));
         pp[k] = *reinterpret_cast<const float4*>(smem + rec);
-        pth[k] = lds_f32(smem, rec + 16);
+        if constexpr (kPaced) {
+            const float4 q = *reinterpret_cast<const float4*>(smem + rec + 16);
+            pth[k] = q.x;
+            pga[k] = q.y;
+            pta[k] = q.z;
+        } else {
+            pth[k] = lds_f32(smem, rec + 16);
+        }
     }
     float nd = __builtin_inff(), ns = 0.0f;
     float d_up = __builtin_inff(), s_up = 0.0f;
@@ -142,7 +163,14 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
             const uint32_t rec = sl.rec[k - kPf];
             pu[k - kPf] = lds_f32(smem, ubias + (rec << 3));
             pp[k - kPf] = *reinterpret_cast<const float4*>(smem + rec);
-            pth[k - kPf] = lds_f32(smem, rec + 16);
+            if constexpr (kPaced) {
+                const float4 q = *reinterpret_cast<const float4*>(smem + rec + 16);
+                pth[k - kPf] = q.x;
+                pga[k - kPf] = q.y;
+                pta[k - kPf] = q.z;
+            } else {
+                pth[k - kPf] = lds_f32(smem, rec + 16);
+            }
         }
         const float d = sl.d[k];
         const float s = sl.s[k];
@@ -152,6 +180,7 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
         // Eq. 1
         const float4 p = pp[k];
         float R = p.z + p.w * d;
+        if constexpr (kPaced) R = R + pga[k] * fminf(tf, pta[k]);
         float x = p.x + p.y * pu[k];
         // min of two positive steps (ns = 0 only when nobody is ahead)
         float s_min = __uint_as_float(min(__float_as_uint(s), __float_as_uint(ns)));
@@ -290,7 +319,7 @@ __device__ __forceinline__ void slots_restore(Slots<N>& sl) {
 // Lanes whose simulation has ended keep stepping with the others (their
 // results are no longer recorded), so the tick needs no divergent branch.
 // Winners go to the LDS histogram `hist`; competitor-steps add to `steps`.
-template <int N>
+template <int N, bool kPaced = false>
 __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t pbase,
                                                float L, const float* __restrict__ d0,
                                                const float* __restrict__ s0,
@@ -304,7 +333,8 @@ __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32
     uint32_t t = t0;
     int nfin = 0, winner = -1;
     while (__builtin_amdgcn_ballot_w64(live)) {
-        const uint32_t cross = slots_tick<N>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
+        const uint32_t cross =
+            slots_tick<N, kPaced>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
         if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
             if (live && cross) {
                 const int k = slots_rank<N>(sl, cross, L, smem, ucol, pbase, nfin, winner, row);

@@ -62,6 +62,20 @@ def competitor_params(rng: np.random.Generator, n: int, dt: float = 1.0) -> np.n
     return out
 
 
+def pace_params(rng: np.random.Generator, comp: np.ndarray, gamma_hi: float = 0.0015,
+                tau_hi: int = 300) -> np.ndarray:
+    """Competitor rows with the time term of the responsiveness appended:
+    [n, 7] float32, gamma ~ U(-gamma_hi, gamma_hi) per tick (fading or
+    strengthening by up to 0.45 over a 300-tick race), tau ~ U{0..tau_hi}
+    ticks."""
+    n = comp.shape[0]
+    out = np.zeros((n, 7), dtype=np.float32)
+    out[:, :5] = comp
+    out[:, 5] = rng.uniform(-gamma_hi, gamma_hi, size=n)
+    out[:, 6] = rng.integers(0, tau_hi + 1, size=n)
+    return out
+
+
 def start_config(cfg: dict) -> dict:
     """A plain Monte-Carlo workload from the start line."""
     rng = np.random.default_rng(cfg["param_seed"])

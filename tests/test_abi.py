@@ -175,3 +175,27 @@ def test_rp_views_reject_before_device_work(L):
     assert L.bbe_rp_views(buf, -1, 5, 20, buf, buf, None) == _bbe.EINVAL
     assert L.bbe_rp_views(None, 10, 5, 20, buf, buf, None) == _bbe.EINVAL
     assert L.bbe_rp_views(buf, 10, 5, 20, None, None, None) == _bbe.EINVAL
+
+
+def test_set_pace_rejects_and_leaves_the_race_unchanged(L):
+    race = _bbe.Race(np.array(GOOD, np.float32), 2000.0)
+    h = race.handle
+    good_g = np.array([0.001, -0.001, 0.0], np.float32)
+    good_t = np.array([100, 200, 0], np.float32)
+    assert L.bbe_race_set_pace(h, good_g.ctypes.data, good_t.ctypes.data) == _bbe.OK
+    bad = [
+        ([np.nan, 0, 0], [1, 1, 1]), ([np.inf, 0, 0], [1, 1, 1]), ([0, 0, 0], [-1, 0, 0]),
+        ([0, 0, 0], [1.5, 0, 0]), ([0, 0, 0], [2.0**25, 0, 0]),
+        ([-0.01, 0, 0], [90, 0, 0]),  # 1 - 0.1 - 0.9 = 0 < 2^-10
+    ]
+    for g, t in bad:
+        g = np.array(g, np.float32)
+        t = np.array(t, np.float32)
+        assert L.bbe_race_set_pace(h, g.ctypes.data, t.ctypes.data) == _bbe.EINVAL, (g, t)
+        assert L.bbe_last_error().decode()
+    assert L.bbe_race_set_pace(None, good_g.ctypes.data, good_t.ctypes.data) == _bbe.EINVAL
+    assert L.bbe_race_set_pace(h, None, good_t.ctypes.data) == _bbe.EINVAL
+    with pytest.raises(_bbe.BBEError):
+        _bbe.Race(np.array([[5, 8, 1, 0.1, 2, -0.01, 90]] * 2, np.float32), 2000.0)
+    with pytest.raises(_bbe.BBEError):
+        _bbe.Race(np.zeros((3, 6), np.float32), 2000.0)
