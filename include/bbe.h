@@ -83,6 +83,21 @@ typedef struct bbe_state {
  * Errors: BBE_EINVAL, BBE_ENOMEM.                                          */
 int bbe_race_init(const bbe_competitor *comp, int n, float track_len, bbe_race **out);
 
+/* Preference coefficients from race factors (paper Section 3: P_c(f_r, p_c)
+ * in [0, 1] reduces a competitor's stochastic step by an amount that grows
+ * with the mismatch between the race's factors, such as going or terrain,
+ * and the competitor's preferred values):
+ *   P_c = prod_k fl(1 - fl(w_ck * |fl(f_k - p_ck)|)),
+ * in single precision, k = 0 .. n_factors-1 in order.  Host inputs: factors
+ * float[n_factors] and prefs float[n][n_factors], all in [0, 1]; sens
+ * float[n][n_factors], each in [0, 1).  Host output pref_out float[n], in
+ * (0, 1]: the `pref` of each bbe_competitor.  No device work.
+ * Errors: BBE_EINVAL (a value out of range, or a product that underflows
+ * to 0).                                                                   */
+#define BBE_MAX_FACTORS 64
+int bbe_pref_from_factors(const float *factors, int n_factors, const float *prefs,
+                          const float *sens, int n, float *pref_out);
+
 /* Gives the competitors' responsiveness a time term (paper Section 3: R_c
  * depends on time as well as on the positions, to model a competitor that
  * starts fast and fades, or starts slow and finishes strongly):

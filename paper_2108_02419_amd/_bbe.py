@@ -55,6 +55,7 @@ SIGNATURES = {
     "bbe_race_free": (None, [_P]),
     "bbe_race_n": (_I, [_P]),
     "bbe_race_set_pace": (_I, [_P, _P, _P]),
+    "bbe_pref_from_factors": (_I, [_P, _I, _P, _P, _I, _P]),
     "bbe_race_sim": (_I, [_P, _P, _U32, _U32, _U64, _U32, _I, _P, _P, _P, _P]),
     "bbe_win_probs": (_I, [_P, _I, _I, _I, _P, _P]),
     "bbe_race_prefix": (_I, [_P, _P, _U64, _U32, _U32, _F, _P, _P, _P, _P]),
@@ -473,3 +474,17 @@ def rp_views(wins, n: int, views=None, counts=None, stream=None):
     uint8 [B] and/or counts int32 (uint32 bits) [n]."""
     _check(lib().bbe_rp_views(_dptr(wins), int(wins.shape[0]), int(n), int(wins.shape[1]),
                               _dptr(views), _dptr(counts), _stream(stream)))
+
+
+def pref_from_factors(factors, prefs, sens) -> np.ndarray:
+    """``bbe_pref_from_factors`` on host arrays: factors [F], prefs and sens
+    [n, F]; returns P [n] (float32)."""
+    f = np.ascontiguousarray(factors, dtype=np.float32)
+    p = np.ascontiguousarray(prefs, dtype=np.float32)
+    w = np.ascontiguousarray(sens, dtype=np.float32)
+    if p.ndim != 2 or p.shape != w.shape or p.shape[1] != f.shape[0]:
+        raise BBEError(EINVAL, "prefs and sens must be [n, F] with F = len(factors)")
+    out = np.empty(p.shape[0], dtype=np.float32)
+    _check(lib().bbe_pref_from_factors(f.ctypes.data, int(f.shape[0]), p.ctypes.data,
+                                       w.ctypes.data, int(p.shape[0]), out.ctypes.data))
+    return out

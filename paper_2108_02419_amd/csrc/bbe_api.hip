@@ -66,6 +66,36 @@ BBE_API int bbe_race_set_pace(bbe_race* race, const float* gamma, const float* t
     return ok();
 }
 
+BBE_API int bbe_pref_from_factors(const float* factors, int n_factors, const float* prefs,
+                                  const float* sens, int n, float* pref_out) {
+    if (!factors || !prefs || !sens || !pref_out) return fail(BBE_EINVAL, "NULL argument");
+    if (n < 1 || n > BBE_MAX_COMPETITORS)
+        return fail(BBE_EINVAL, "n must be in 1..%d", BBE_MAX_COMPETITORS);
+    if (n_factors < 1 || n_factors > BBE_MAX_FACTORS)
+        return fail(BBE_EINVAL, "n_factors must be in 1..%d", BBE_MAX_FACTORS);
+    auto unit = [](float v) { return std::isfinite(v) && v >= 0.0f && v <= 1.0f; };
+    for (int k = 0; k < n_factors; ++k)
+        if (!unit(factors[k])) return fail(BBE_EINVAL, "factor %d must be in [0, 1]", k);
+    for (int i = 0; i < n * n_factors; ++i) {
+        if (!unit(prefs[i])) return fail(BBE_EINVAL, "preference %d must be in [0, 1]", i);
+        if (!(std::isfinite(sens[i]) && sens[i] >= 0.0f && sens[i] < 1.0f))
+            return fail(BBE_EINVAL, "sensitivity %d must be in [0, 1)", i);
+    }
+    for (int c = 0; c < n; ++c) {
+        // one rounding per operation, factors in order
+        float P = 1.0f;
+        for (int k = 0; k < n_factors; ++k) {
+            const float mismatch = std::fabs(factors[k] - prefs[c * n_factors + k]);
+            const float wm = sens[c * n_factors + k] * mismatch;
+            const float term = 1.0f - wm;
+            P = P * term;
+        }
+        if (!(P > 0.0f)) return fail(BBE_EINVAL, "competitor %d: P underflows to 0", c);
+        pref_out[c] = P;
+    }
+    return ok();
+}
+
 BBE_API void bbe_race_free(bbe_race* race) { delete race; }
 
 BBE_API int bbe_race_n(const bbe_race* race) {

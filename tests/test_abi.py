@@ -199,3 +199,27 @@ def test_set_pace_rejects_and_leaves_the_race_unchanged(L):
         _bbe.Race(np.array([[5, 8, 1, 0.1, 2, -0.01, 90]] * 2, np.float32), 2000.0)
     with pytest.raises(_bbe.BBEError):
         _bbe.Race(np.zeros((3, 6), np.float32), 2000.0)
+
+
+def test_pref_from_factors_host_function(L):
+    """A host-only entry point (no device work): equals the oracle bit for
+    bit, and rejects out-of-range values."""
+    from oracle.factors import pref_from_factors as oracle_pref
+    rng = np.random.default_rng(8)
+    for n, F in ((1, 1), (5, 3), (20, 64), (7, 17)):
+        f = rng.uniform(0, 1, F).astype(np.float32)
+        p = rng.uniform(0, 1, (n, F)).astype(np.float32)
+        w = rng.uniform(0, 0.6, (n, F)).astype(np.float32)
+        np.testing.assert_array_equal(_bbe.pref_from_factors(f, p, w), oracle_pref(f, p, w))
+    good = (np.float32([0.5]), np.float32([[0.5]]), np.float32([[0.5]]))
+    for k, v in ((0, 1.5), (0, -0.1), (1, np.nan), (2, 1.0), (2, -0.5)):
+        args = [a.copy() for a in good]
+        args[k].flat[0] = v
+        with pytest.raises(_bbe.BBEError):
+            _bbe.pref_from_factors(*args)
+    with pytest.raises(_bbe.BBEError):
+        _bbe.pref_from_factors(np.zeros(65, np.float32), np.zeros((1, 65), np.float32),
+                               np.zeros((1, 65), np.float32))
+    with pytest.raises(_bbe.BBEError):  # underflow
+        _bbe.pref_from_factors(np.zeros(64, np.float32), np.ones((1, 64), np.float32),
+                               np.full((1, 64), 0.9999999, np.float32))
