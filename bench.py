@@ -129,7 +129,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the Monte-Carlo "
-              "shards by simulation range across GPUs but this build measures a single GPU.",
+              "shards by simulation range across GPUs, but bench.py measures a single GPU.",
               file=sys.stderr)
         return 2
 

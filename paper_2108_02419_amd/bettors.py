@@ -174,7 +174,7 @@ def main():
     ap.add_argument("--max-rounds", type=int, default=None)
     ap.add_argument("--judge-every", type=int, default=25)
     ap.add_argument("--cheap", type=int, default=100_000, help="LinEx/LW/UD/ZI bettors")
-    ap.add_argument("--out", default="gpurun_out/bettors.json")
+    ap.add_argument("--out", default="bbe_out/bettors.json")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()

@@ -11,7 +11,7 @@ audit sample is also answered by Monte-Carlo; a high-sample Monte-Carlo
 judge measures the error of both.  Orchestration only -- every computation
 runs in the library's kernels.
 
-    python -m paper_2108_02419_amd.query_loop --params gpurun_out/surrogate/params.npy
+    python -m paper_2108_02419_amd.query_loop --params bbe_out/surrogate/params.npy
 """
 from __future__ import annotations
 
@@ -168,7 +168,7 @@ def main():
                     help="surrogate entropy above which a state goes to Monte-Carlo: a number, "
                          "or 'auto' for the calibrated gate in result.json beside --params "
                          "(default 0.95 ln n)")
-    ap.add_argument("--out", default="gpurun_out/query_loop.json")
+    ap.add_argument("--out", default="bbe_out/query_loop.json")
     args = ap.parse_args()
     torch.cuda.set_device(0)
     params = np.load(args.params)

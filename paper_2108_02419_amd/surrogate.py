@@ -266,7 +266,7 @@ def main():
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=4)
-    ap.add_argument("--out", default="gpurun_out/surrogate")
+    ap.add_argument("--out", default="bbe_out/surrogate")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
 
