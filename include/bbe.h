@@ -408,6 +408,17 @@ void bbe_mlp_free(bbe_mlp *m);
 /* Copies the float32 master parameters to host memory.  Synchronous.       */
 int bbe_mlp_get_params(const bbe_mlp *m, float *params);
 
+/* Saves a network's parameters to a file (host path): the 8 bytes
+ * "BBEMLP01", the parameter count as uint32 (little endian), then the
+ * float32 parameters in the packing above.  Synchronous.
+ * Errors: BBE_EINVAL (NULL argument, file not writable), BBE_EDEVICE.       */
+int bbe_mlp_save(const bbe_mlp *m, const char *path);
+
+/* Creates a network (as bbe_mlp_create, with max_batch) from a file written
+ * by bbe_mlp_save.  Errors: BBE_EINVAL (missing or malformed file, or what
+ * bbe_mlp_create rejects), BBE_ENOMEM, BBE_EDEVICE.                          */
+int bbe_mlp_load(const char *path, int max_batch, bbe_mlp **out);
+
 /* Inference on `batch` rows (any size).  Device outputs, each optional:
  * probs float [batch][20] (0 in empty slots), entropy float [batch]
  * (natural log), logits float [batch][32] (-inf in empty slots).           */

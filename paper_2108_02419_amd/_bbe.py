@@ -70,6 +70,8 @@ SIGNATURES = {
     "bbe_mlp_create": (_I, [_P, _I, _P]),
     "bbe_mlp_free": (None, [_P]),
     "bbe_mlp_get_params": (_I, [_P, _P]),
+    "bbe_mlp_save": (_I, [_P, ctypes.c_char_p]),
+    "bbe_mlp_load": (_I, [ctypes.c_char_p, _I, _P]),
     "bbe_mlp_forward": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
     "bbe_mlp_loss_grad": (_I, [_P, _P, _P, _P, _I, _P, _P, _P]),
     "bbe_mlp_adam_step": (_I, [_P, _P, _F, _P]),
@@ -371,6 +373,18 @@ class Mlp:
         out = np.empty(MLP_NPARAMS, dtype=np.float32)
         _check(lib().bbe_mlp_get_params(self._h, out.ctypes.data))
         return out
+
+    def save(self, path: str):
+        _check(lib().bbe_mlp_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path: str, max_batch: int) -> "Mlp":
+        h = ctypes.c_void_p()
+        _check(lib().bbe_mlp_load(os.fsencode(path), int(max_batch), ctypes.byref(h)))
+        m = cls.__new__(cls)
+        m._h = h
+        m.max_batch = int(max_batch)
+        return m
 
     def forward(self, x, n_valid, probs=None, entropy=None, logits=None, stream=None):
         _check(lib().bbe_mlp_forward(self._h, _dptr(x), _dptr(n_valid), int(x.shape[0]),

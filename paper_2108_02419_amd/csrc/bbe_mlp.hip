@@ -154,6 +154,46 @@ BBE_API int bbe_mlp_get_params(const bbe_mlp* m, float* params) {
     return ok();
 }
 
+// File layout: 8-byte magic "BBEMLP01", uint32 parameter count (little
+// endian), then the float32 master parameters in the packing of
+// BBE_MLP_NPARAMS.
+static const char kMagic[8] = {'B', 'B', 'E', 'M', 'L', 'P', '0', '1'};
+
+BBE_API int bbe_mlp_save(const bbe_mlp* m, const char* path) {
+    if (!m || !path) return fail(BBE_EINVAL, "NULL argument");
+    std::vector<float> p((size_t)bbe::kNParams);
+    int rc = bbe_mlp_get_params(m, p.data());
+    if (rc != BBE_OK) return rc;
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(BBE_EINVAL, "cannot open %s for writing", path);
+    const uint32_t count = (uint32_t)bbe::kNParams;
+    bool good = std::fwrite(kMagic, 1, 8, f) == 8 && std::fwrite(&count, 4, 1, f) == 1 &&
+                std::fwrite(p.data(), sizeof(float), p.size(), f) == p.size();
+    good = (std::fclose(f) == 0) && good;
+    if (!good) return fail(BBE_EINVAL, "writing %s failed", path);
+    return ok();
+}
+
+BBE_API int bbe_mlp_load(const char* path, int max_batch, bbe_mlp** out) {
+    if (!out) return fail(BBE_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!path) return fail(BBE_EINVAL, "path is NULL");
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(BBE_EINVAL, "cannot open %s", path);
+    char magic[8];
+    uint32_t count = 0;
+    std::vector<float> p((size_t)bbe::kNParams);
+    bool good = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
+                std::fread(&count, 4, 1, f) == 1 && count == (uint32_t)bbe::kNParams &&
+                std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
+    char extra;
+    good = good && std::fread(&extra, 1, 1, f) == 0;  // nothing after the parameters
+    std::fclose(f);
+    if (!good) return fail(BBE_EINVAL, "%s is not a saved network of %d parameters", path,
+                           bbe::kNParams);
+    return bbe_mlp_create(p.data(), max_batch, out);
+}
+
 BBE_API int bbe_mlp_forward(const bbe_mlp* m, const uint16_t* x, const int32_t* n_valid,
                             int batch, float* probs, float* entropy, float* logits,
                             void* stream) {

@@ -223,3 +223,21 @@ def test_pref_from_factors_host_function(L):
     with pytest.raises(_bbe.BBEError):  # underflow
         _bbe.pref_from_factors(np.zeros(64, np.float32), np.ones((1, 64), np.float32),
                                np.full((1, 64), 0.9999999, np.float32))
+
+
+def test_mlp_load_rejects_bad_files(L, tmp_path):
+    out = ctypes.c_void_p()
+    assert L.bbe_mlp_load(str(tmp_path / "missing.bin").encode(), 8, ctypes.byref(out)) == _bbe.EINVAL
+    bad_magic = tmp_path / "magic.bin"
+    bad_magic.write_bytes(b"NOTANMLP" + (177940).to_bytes(4, "little") + bytes(4 * 177940))
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"BBEMLP01" + (177940).to_bytes(4, "little") + bytes(4 * 1000))
+    wrong_count = tmp_path / "count.bin"
+    wrong_count.write_bytes(b"BBEMLP01" + (5).to_bytes(4, "little") + bytes(20))
+    longer = tmp_path / "long.bin"
+    longer.write_bytes(b"BBEMLP01" + (177940).to_bytes(4, "little") + bytes(4 * 177940 + 1))
+    for f in (bad_magic, short, wrong_count, longer):
+        assert L.bbe_mlp_load(str(f).encode(), 8, ctypes.byref(out)) == _bbe.EINVAL, f
+        assert L.bbe_last_error().decode()
+    assert L.bbe_mlp_load(None, 8, ctypes.byref(out)) == _bbe.EINVAL
+    assert L.bbe_mlp_save(None, b"/tmp/x") == _bbe.EINVAL

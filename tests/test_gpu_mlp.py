@@ -130,3 +130,29 @@ def test_training_reduces_loss(torch):
         losses.append(loss.item())
     ent = float(np.mean([-(t[t > 0] * np.log(t[t > 0])).sum() for t in T]))
     assert losses[-1] < losses[0] - 0.5 * (losses[0] - ent), (losses[0], losses[-1], ent)
+
+
+def test_save_and_load_round_trip(torch, tmp_path):
+    """A network trained for a few steps, saved and loaded: identical
+    parameters and identical forward outputs."""
+    rng = np.random.default_rng(5)
+    net = _bbe.Mlp(inputs.surrogate_init(4), max_batch=64)
+    X, n, T = _features(rng, 64)
+    xt, nt = _bits(torch, X), torch.tensor(n, device="cuda")
+    tt = torch.tensor(T, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        net.train_step(xt, nt, tt, 1e-3, loss)
+    torch.cuda.synchronize()
+    path = str(tmp_path / "net.bin")
+    announce("mlp save/load")
+    net.save(path)
+    back = _bbe.Mlp.load(path, max_batch=8)
+    np.testing.assert_array_equal(back.params(), net.params())
+    outs = []
+    for m in (net, back):
+        probs = torch.empty((64, 20), dtype=torch.float32, device="cuda")
+        m.forward(xt, nt, probs)
+        torch.cuda.synchronize()
+        outs.append(probs.cpu().numpy())
+    np.testing.assert_array_equal(outs[0], outs[1])
