@@ -98,3 +98,29 @@ def test_paced_trace_and_prefix(torch, orc):
         assert int(t.item()) == ot
         np.testing.assert_array_equal(p.cpu().numpy(), op)
         np.testing.assert_array_equal(q.cpu().numpy(), oq)
+
+
+def test_paced_prefix_batch(torch, orc):
+    """The batched in-play state generator with paced and plain races."""
+    from paper_2108_02419_amd import _bbe
+    rng = np.random.default_rng(33)
+    comps, targets = [], []
+    for i in range(64):
+        comp = inputs.competitor_params(rng, int(rng.integers(2, 21)))
+        comps.append(inputs.pace_params(rng, comp) if i % 3 else comp)
+        targets.append(float(rng.uniform(0.0, 1800.0)))
+    specs = [(Race(c, L), None, 0, 1, 0x80000000 | i, 0) for i, c in enumerate(comps)]
+    n = len(specs)
+    tick = torch.zeros(n, dtype=torch.int32, device="cuda")
+    pos = torch.zeros((n, 20), dtype=torch.float32, device="cuda")
+    prev = torch.zeros((n, 20), dtype=torch.float32, device="cuda")
+    announce("paced prefix batch of 64")
+    _bbe.prefix_batch(specs, np.zeros(n, np.uint32), targets, 9, tick, pos, prev)
+    torch.cuda.synchronize()
+    T, P, V = tick.cpu().numpy().view(np.uint32), pos.cpu().numpy(), prev.cpu().numpy()
+    for i, c in enumerate(comps):
+        ot, op, oq = orc.race_prefix(c, L, 9, 0x80000000 | i, 0, targets[i])
+        m = c.shape[0]
+        assert T[i] == ot
+        np.testing.assert_array_equal(P[i, :m], op)
+        np.testing.assert_array_equal(V[i, :m], oq)
