@@ -96,16 +96,33 @@ def cpu_baseline(c, target_s: float = 12.0):
     oracle.race_sim(c["comp"], c["L"], probe, c["seed"], request=c["request"],
                     stop_after=c["stop_after"], want_orders=False, threads=threads)
     dt = time.perf_counter() - t0
-    sample = int(min(max(probe, probe * target_s / max(dt, 1e-6)), 200_000))
+    sample = int(min(max(probe, probe * target_s / max(dt, 1e-6)), 800_000))
     t0 = time.perf_counter()
     _, wins, steps = oracle.race_sim(c["comp"], c["L"], sample, c["seed"], request=c["request"],
                                      stop_after=c["stop_after"], want_orders=False,
                                      threads=threads)
     dt = time.perf_counter() - t0
+    # the same oracle on one thread, on a tenth of that sample
+    one = max(200, sample // 10)
+    t1 = time.perf_counter()
+    _, _, steps1 = oracle.race_sim(c["comp"], c["L"], one, c["seed"], request=c["request"],
+                                   stop_after=c["stop_after"], want_orders=False, threads=1)
+    dt1 = time.perf_counter() - t1
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": sample / dt, "unit": "sims/s", "cores": threads, "kind": "oracle",
             "sample": f"first {sample} simulations of the same workload "
                       f"({steps} competitor-steps, {dt:.2f} s)",
-            "competitor_steps_per_s": steps / dt}
+            "competitor_steps_per_s": steps / dt,
+            "single_thread": {"value": one / dt1, "unit": "sims/s",
+                              "sample": f"first {one} simulations ({dt1:.2f} s)",
+                              "competitor_steps_per_s": steps1 / dt1},
+            "host": {"cpu_model": model, "nproc": os.cpu_count()}}
 
 
 def main() -> int:
@@ -116,7 +133,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
-    ap.add_argument("--batch-steps", type=int, default=5)
+    ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--no-gated", action="store_true",
                     help="skip the trained, gated surrogate leg")
     ap.add_argument("--no-bettors", action="store_true",
@@ -334,7 +351,8 @@ def batch_leg(steps: int):
     return {"workload": "batch_inplay_4096: 4096 requests, n 5-20, remaining 5-100% of 2000, "
                         "100-10^4 sims each, full finish order, one persistent graph launch",
             "requests": n, "sims": sims, "competitor_steps": csteps,
-            "ms_per_launch": {"median": ms[len(ms) // 2], "min": ms[0]},
+            "ms_per_launch": {"median": ms[len(ms) // 2], "min": ms[0],
+                              "cov": float(np.std(ms) / np.mean(ms))},
             "sims_per_s": sims / med, "competitor_steps_per_s": csteps / med,
             "alu_frac": csteps * ALGO_OPS_PER_COMPETITOR_STEP / med / VALU_PEAK_OPS,
             "plan": plan.info(), "plan_setup_s": setup_s}
