@@ -102,8 +102,8 @@ def cpu_baseline(c, target_s: float = 12.0):
                                      stop_after=c["stop_after"], want_orders=False,
                                      threads=threads)
     dt = time.perf_counter() - t0
-    # the same oracle on one thread, on a tenth of that sample
-    one = max(200, sample // 10)
+    # the same oracle on one thread, on a fortieth of that sample
+    one = max(200, sample // 40)
     t1 = time.perf_counter()
     _, _, steps1 = oracle.race_sim(c["comp"], c["L"], one, c["seed"], request=c["request"],
                                    stop_after=c["stop_after"], want_orders=False, threads=1)
