@@ -109,7 +109,8 @@ int bbe_pref_from_factors(const float *factors, int n_factors, const float *pref
  * 0..2^24; a slowing term must keep 1 - |rho_c| + gamma_c*tau_c >= 2^-10,
  * and the race must still end within BBE_EXPECTED_TICK_BOUND ticks at its
  * slowest.  All zeros (the state after bbe_race_init) is the plain race;
- * races with some gamma != 0 run kernels that evaluate the term.
+ * races with some gamma != 0 run kernels that evaluate the term.  The
+ * surrogate's state encoding (bbe_encode_states) carries no time term.
  * Errors: BBE_EINVAL (the race is left unchanged).                         */
 int bbe_race_set_pace(bbe_race *race, const float *gamma, const float *tau);
 
