@@ -49,6 +49,15 @@ def test_linex_by_hand():
     assert B.view(B.LINEX, 4, tr, 0, L, 0, 0, 1) == 0
 
 
+def test_linex_window_is_the_whole_trace_when_n_exceeds_it():
+    # over both ticks comp 0 is faster (12 vs 9 du), over the last tick comp 1 (8 vs 2)
+    tr = np.float32([[0, 5], [10, 6], [12, 14]])
+    L = 100.0
+    assert B.view(B.LINEX, 50, tr, 2, L, 0, 0, 1) == 0  # w = min(50, 2) = 2
+    assert B.view(B.LINEX, 2, tr, 2, L, 0, 0, 1) == 0
+    assert B.view(B.LINEX, 1, tr, 2, L, 0, 0, 1) == 1
+
+
 def test_linex_window_changes_the_pick():
     # comp 1 had a fast first tick, then slowed down
     tr = np.float32([[35, 30], [40, 39], [45, 44]])
