@@ -11,13 +11,15 @@
 namespace bbe {
 
 // Per-wave LDS: draw table [kMaxN][64] floats, parameter records, win
-// histogram, and the request's start state in slot order (positions,
-// previous steps, competitor ids) so that it does not occupy registers.
+// histogram, the request's start state in slot order (positions, previous
+// steps, competitor ids) so that it does not occupy registers, and the
+// byte table the ranking of several same-tick finishers uses.
 constexpr uint32_t kWaveU = kMaxN * 256;
 constexpr uint32_t kWavePar = kMaxN * 32;
 constexpr uint32_t kWaveHist = 128;
 constexpr uint32_t kWaveInit = kMaxN * 12;
-constexpr uint32_t kWaveBytes = kWaveU + kWavePar + kWaveHist + kWaveInit;
+constexpr uint32_t kWaveIds = kMaxN * 64;  // finisher ids of a tick, u8[N][64]
+constexpr uint32_t kWaveBytes = kWaveU + kWavePar + kWaveHist + kWaveInit + kWaveIds;
 
 __device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v) {
 #pragma unroll
@@ -31,6 +33,7 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
                                           unsigned long long* wins_row,
                                           unsigned long long& steps) {
     const uint32_t ucol = wbase + lane * 4;
+    const uint32_t icol = wbase + kWaveU + kWavePar + kWaveHist + kWaveInit + lane;
     const uint32_t pbase = wbase + kWaveU;
     uint32_t* hist = reinterpret_cast<uint32_t*>(smem + wbase + kWaveU + kWavePar);
     float* d0 = reinterpret_cast<float*>(smem + wbase + kWaveU + kWavePar + kWaveHist);
@@ -50,7 +53,7 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
         // re-read the start state from LDS each generation rather than
         // keeping 3N registers live across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced>(smem, ucol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim,
+        run_generation<N, kPaced>(smem, ucol, icol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim,
                           rq.request, k0, k1, rq.stop_after, nullptr, hist, steps);
     }
     if (lane < N) {

@@ -19,7 +19,8 @@ struct BlockLds {
     static constexpr uint32_t kWins = kPar + 1024;                        // u32[N]
     static constexpr uint32_t kSteps = kWins + 128;                        // u64
     static constexpr uint32_t kInit = kSteps + 16;  // start state: d0, s0 (f32[N]), id0 (u8[N])
-    static constexpr uint32_t kBytes = kInit + kMaxN * 12;
+    static constexpr uint32_t kIds = kInit + kMaxN * 12;  // [wave] finisher ids, u8[N][64]
+    static constexpr uint32_t kBytes = kIds + kWaves * N * 64;
 };
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
@@ -44,6 +45,7 @@ __global__ void __launch_bounds__(kBlock)
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint32_t ucol = Lay::kU + wave * (N * 256) + lane * 4;
+    const uint32_t icol = Lay::kIds + wave * (N * 64) + lane;
     // one record table for the workgroup (every wave simulates the same
     // race), at a compile-time offset
     const uint32_t pbase = Lay::kPar;
@@ -76,7 +78,7 @@ __global__ void __launch_bounds__(kBlock)
         // re-read the start state from LDS each generation rather than
         // keeping it live (in registers) across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced>(smem, ucol, pbase, L, s_d0, s_s0, s_id0, a.t0, live,
+        run_generation<N, kPaced>(smem, ucol, icol, pbase, L, s_d0, s_s0, s_id0, a.t0, live,
                           a.sim_begin + (uint32_t)j, a.request, a.k0, a.k1, a.stop_after, row,
                           s_wins, steps);
     }

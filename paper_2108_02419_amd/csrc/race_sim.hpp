@@ -202,12 +202,18 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
 
 // Step 5 (ranking): ranks this tick's finishers (slot mask `cross`) after
 // the `nfin` earlier ones and records them; returns the number ranked.  A
-// lone finisher needs no fraction; several are ordered by their fractions,
-// staged in the lane's (already consumed) column of the draw table.
+// lone finisher needs no fraction.  Several are compacted first -- entry j
+// (the j-th set bit of `cross`) holds the finisher's fraction in the lane's
+// (already consumed) column of the draw table, at ucol + 256*j, and its
+// competitor index in the lane's column of a byte table, at icol + 64*j --
+// and then picked in (fraction, index) order by a selection over those c
+// entries, so the work grows with c^2 for the few finishers of a tick
+// rather than with c*N.
 template <int N>
 __device__ __forceinline__ int slots_rank(const Slots<N>& sl, uint32_t cross, float L,
-                                          char* smem, uint32_t ucol, uint32_t pbase, int nfin,
-                                          int& winner, uint8_t* __restrict__ row) {
+                                          char* smem, uint32_t ucol, uint32_t icol,
+                                          uint32_t pbase, int nfin, int& winner,
+                                          uint8_t* __restrict__ row) {
     if ((cross & (cross - 1u)) == 0u) {
         uint32_t rec = 0u;
 #pragma unroll
@@ -219,31 +225,32 @@ __device__ __forceinline__ int slots_rank(const Slots<N>& sl, uint32_t cross, fl
     }
 #pragma unroll
     for (int k = 0; k < N; ++k)
-        if ((cross >> k) & 1u) lds_st_f32(smem, ucol + 256u * k, (L - sl.d[k]) / sl.s[k]);
-    int ranked = 0;
-    uint32_t rem = cross;
-    while (rem) {
-        int bk = -1;
-        float bf = 0.0f;
-        uint32_t brec = 0xFFFFFFFFu;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            if (!((rem >> k) & 1u)) continue;
-            const uint32_t rk = sl.rec[k];
-            const float f = lds_f32(smem, ucol + 256u * k);
-            const bool better = (bk < 0) || (f < bf) || (f == bf && rk < brec);
-            bk = better ? k : bk;
-            bf = better ? f : bf;
-            brec = better ? rk : brec;
+        if ((cross >> k) & 1u) {
+            const uint32_t j = __builtin_popcount(cross & ((1u << k) - 1u));
+            lds_st_f32(smem, ucol + 256u * j, (L - sl.d[k]) / sl.s[k]);
+            smem[icol + 64u * j] = (char)((sl.rec[k] - pbase) >> 5);
         }
-        const uint32_t bid = (brec - pbase) >> 5;
-        const int r = nfin + ranked;
-        if (r == 0) winner = (int)bid;
-        if (row) row[r] = (uint8_t)bid;
-        ++ranked;
-        rem &= ~(1u << bk);
+    const int c = __builtin_popcount(cross);
+    uint32_t used = 0u;
+    for (int r = 0; r < c; ++r) {
+        int bj = -1;
+        float bf = 0.0f;
+        uint32_t bid = 0u;
+        for (int j = 0; j < c; ++j) {
+            const float f = lds_f32(smem, ucol + 256u * j);
+            const uint32_t id = (uint8_t)smem[icol + 64u * j];
+            const bool better =
+                !((used >> j) & 1u) && ((bj < 0) || (f < bf) || (f == bf && id < bid));
+            bj = better ? j : bj;
+            bf = better ? f : bf;
+            bid = better ? id : bid;
+        }
+        used |= 1u << bj;  // c - r > 0 entries are unused, so bj >= 0
+        const int rr = nfin + r;
+        if (rr == 0) winner = (int)bid;
+        if (row) row[rr] = (uint8_t)bid;
     }
-    return ranked;
+    return c;
 }
 
 // Step 5 (parking): the slots of mask `cross` get the parking position.
@@ -320,7 +327,8 @@ __device__ __forceinline__ void slots_restore(Slots<N>& sl) {
 // results are no longer recorded), so the tick needs no divergent branch.
 // Winners go to the LDS histogram `hist`; competitor-steps add to `steps`.
 template <int N, bool kPaced = false>
-__device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t pbase,
+__device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t icol,
+                                               uint32_t pbase,
                                                float L, const float* __restrict__ d0,
                                                const float* __restrict__ s0,
                                                const uint8_t* __restrict__ id0, uint32_t t0,
@@ -337,7 +345,8 @@ __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32
             slots_tick<N, kPaced>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
         if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
             if (live && cross) {
-                const int k = slots_rank<N>(sl, cross, L, smem, ucol, pbase, nfin, winner, row);
+                const int k =
+                    slots_rank<N>(sl, cross, L, smem, ucol, icol, pbase, nfin, winner, row);
                 nfin += k;
                 steps += (unsigned long long)k * (t + 1 - t0);
             }
