@@ -200,37 +200,35 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
     return cross;
 }
 
-// Step 5 (ranking): ranks this tick's finishers (slot mask `cross`) after
-// the `nfin` earlier ones and records them; returns the number ranked.  A
-// lone finisher needs no fraction.  Several are compacted first -- entry j
-// (the j-th set bit of `cross`) holds the finisher's fraction in the lane's
-// (already consumed) column of the draw table, at ucol + 256*j, and its
-// competitor index in the lane's column of a byte table, at icol + 64*j --
-// and then picked in (fraction, index) order by a selection over those c
-// entries, so the work grows with c^2 for the few finishers of a tick
-// rather than with c*N.
+// Step 5: ranks this tick's finishers (slot mask `cross`) after the `nfin`
+// earlier ones, records them, and parks every crossing slot (position NaN);
+// returns the number ranked.  `rank` is false in lanes whose simulation has
+// already ended: their finishers are parked but not recorded.  In one pass
+// over the crossing slots, each finisher is compacted -- entry j (the j-th
+// set bit of `cross`) holds its competitor index in the lane's column of a
+// byte table, at icol + 64*j, and, when there are several, its crossing
+// fraction in the lane's (already consumed) column of the draw table, at
+// ucol + 256*j -- and its slot is parked.  The entries are then picked in
+// (fraction, index) order by a selection over those c entries, so the work
+// grows with c^2 for the few finishers of a tick rather than with c*N.
 template <int N>
-__device__ __forceinline__ int slots_rank(const Slots<N>& sl, uint32_t cross, float L,
-                                          char* smem, uint32_t ucol, uint32_t icol,
-                                          uint32_t pbase, int nfin, int& winner,
-                                          uint8_t* __restrict__ row) {
-    if ((cross & (cross - 1u)) == 0u) {
-        uint32_t rec = 0u;
-#pragma unroll
-        for (int k = 0; k < N; ++k) rec = ((cross >> k) & 1u) ? sl.rec[k] : rec;
-        const uint32_t id = (rec - pbase) >> 5;
-        if (nfin == 0) winner = (int)id;
-        if (row) row[nfin] = (uint8_t)id;
-        return 1;
-    }
+__device__ __forceinline__ int slots_rank_park(Slots<N>& sl, uint32_t cross, bool rank, float L,
+                                               char* smem, uint32_t ucol, uint32_t icol,
+                                               uint32_t pbase, int nfin, int& winner,
+                                               uint8_t* __restrict__ row) {
+    const int c = __builtin_popcount(cross);
 #pragma unroll
     for (int k = 0; k < N; ++k)
         if ((cross >> k) & 1u) {
-            const uint32_t j = __builtin_popcount(cross & ((1u << k) - 1u));
-            lds_st_f32(smem, ucol + 256u * j, (L - sl.d[k]) / sl.s[k]);
-            smem[icol + 64u * j] = (char)((sl.rec[k] - pbase) >> 5);
+            if (rank) {
+                const uint32_t j = __builtin_popcount(cross & ((1u << k) - 1u));
+                smem[icol + 64u * j] = (char)((sl.rec[k] - pbase) >> 5);
+                // a lone finisher needs no fraction
+                if (c > 1) lds_st_f32(smem, ucol + 256u * j, (L - sl.d[k]) / sl.s[k]);
+            }
+            sl.d[k] = parked();
         }
-    const int c = __builtin_popcount(cross);
+    if (!rank) return 0;
     uint32_t used = 0u;
     for (int r = 0; r < c; ++r) {
         int bj = -1;
@@ -251,14 +249,6 @@ __device__ __forceinline__ int slots_rank(const Slots<N>& sl, uint32_t cross, fl
         if (row) row[rr] = (uint8_t)bid;
     }
     return c;
-}
-
-// Step 5 (parking): the slots of mask `cross` get the parking position.
-template <int N>
-__device__ __forceinline__ void slots_park(Slots<N>& sl, uint32_t cross) {
-#pragma unroll
-    for (int k = 0; k < N; ++k)
-        if ((cross >> k) & 1u) sl.d[k] = parked();
 }
 
 // Step 6: compare-exchange of slots k and k+1: three v_swap_b32 under the
@@ -344,13 +334,13 @@ __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32
         const uint32_t cross =
             slots_tick<N, kPaced>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
         if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
-            if (live && cross) {
-                const int k =
-                    slots_rank<N>(sl, cross, L, smem, ucol, icol, pbase, nfin, winner, row);
+            const bool rank = live && cross;
+            const int k = slots_rank_park<N>(sl, cross, rank, L, smem, ucol, icol, pbase, nfin,
+                                             winner, row);
+            if (rank) {
                 nfin += k;
                 steps += (unsigned long long)k * (t + 1 - t0);
             }
-            slots_park<N>(sl, cross);
         }
         if (live && (nfin >= stop_after || t + 1 - t0 >= kTickLimit)) {
             if (winner >= 0) atomicAdd(&hist[winner], 1u);
