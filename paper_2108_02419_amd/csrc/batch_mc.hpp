@@ -53,8 +53,9 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
         // re-read the start state from LDS each generation rather than
         // keeping 3N registers live across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced>(smem, ucol, icol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim,
-                          rq.request, k0, k1, rq.stop_after, nullptr, hist, steps);
+        run_generation<N, kPaced, false>(smem, ucol, icol, pbase, rq.rc.L, d0, s0, id0, rq.t0,
+                                         live, sim, rq.request, k0, k1, rq.stop_after, nullptr,
+                                         hist, steps);
     }
     if (lane < N) {
         uint32_t w = hist[lane];

@@ -251,6 +251,67 @@ __device__ __forceinline__ int slots_rank_park(Slots<N>& sl, uint32_t cross, boo
     return c;
 }
 
+// Step 5 (ranking): ranks this tick's finishers (slot mask `cross`) after
+// the `nfin` earlier ones and records them; returns the number ranked.  A
+// lone finisher needs no fraction.  Several are compacted first -- entry j
+// (the j-th set bit of `cross`) holds the finisher's fraction in the lane's
+// (already consumed) column of the draw table, at ucol + 256*j, and its
+// competitor index in the lane's column of a byte table, at icol + 64*j --
+// and then picked in (fraction, index) order by a selection over those c
+// entries, so the work grows with c^2 for the few finishers of a tick
+// rather than with c*N.
+template <int N>
+__device__ __forceinline__ int slots_rank(const Slots<N>& sl, uint32_t cross, float L,
+                                          char* smem, uint32_t ucol, uint32_t icol,
+                                          uint32_t pbase, int nfin, int& winner,
+                                          uint8_t* __restrict__ row) {
+    if ((cross & (cross - 1u)) == 0u) {
+        uint32_t rec = 0u;
+#pragma unroll
+        for (int k = 0; k < N; ++k) rec = ((cross >> k) & 1u) ? sl.rec[k] : rec;
+        const uint32_t id = (rec - pbase) >> 5;
+        if (nfin == 0) winner = (int)id;
+        if (row) row[nfin] = (uint8_t)id;
+        return 1;
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if ((cross >> k) & 1u) {
+            const uint32_t j = __builtin_popcount(cross & ((1u << k) - 1u));
+            lds_st_f32(smem, ucol + 256u * j, (L - sl.d[k]) / sl.s[k]);
+            smem[icol + 64u * j] = (char)((sl.rec[k] - pbase) >> 5);
+        }
+    const int c = __builtin_popcount(cross);
+    uint32_t used = 0u;
+    for (int r = 0; r < c; ++r) {
+        int bj = -1;
+        float bf = 0.0f;
+        uint32_t bid = 0u;
+        for (int j = 0; j < c; ++j) {
+            const float f = lds_f32(smem, ucol + 256u * j);
+            const uint32_t id = (uint8_t)smem[icol + 64u * j];
+            const bool better =
+                !((used >> j) & 1u) && ((bj < 0) || (f < bf) || (f == bf && id < bid));
+            bj = better ? j : bj;
+            bf = better ? f : bf;
+            bid = better ? id : bid;
+        }
+        used |= 1u << bj;  // c - r > 0 entries are unused, so bj >= 0
+        const int rr = nfin + r;
+        if (rr == 0) winner = (int)bid;
+        if (row) row[rr] = (uint8_t)bid;
+    }
+    return c;
+}
+
+// Step 5 (parking): the slots of mask `cross` get the parking position.
+template <int N>
+__device__ __forceinline__ void slots_park(Slots<N>& sl, uint32_t cross) {
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+        if ((cross >> k) & 1u) sl.d[k] = parked();
+}
+
 // Step 6: compare-exchange of slots k and k+1: three v_swap_b32 under the
 // execution mask of the lanes that need the exchange, skipped when none
 // does (the first pass of a tick exchanges most pairs in some lane, later
@@ -316,7 +377,10 @@ __device__ __forceinline__ void slots_restore(Slots<N>& sl) {
 // Lanes whose simulation has ended keep stepping with the others (their
 // results are no longer recorded), so the tick needs no divergent branch.
 // Winners go to the LDS histogram `hist`; competitor-steps add to `steps`.
-template <int N, bool kPaced = false>
+// kRankPark selects slots_rank_park (one pass that ranks and parks) over
+// slots_rank followed by slots_park; the two give the same results, and
+// each kernel takes the one its register allocation does better with.
+template <int N, bool kPaced = false, bool kRankPark = true>
 __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t icol,
                                                uint32_t pbase,
                                                float L, const float* __restrict__ d0,
@@ -334,12 +398,22 @@ __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32
         const uint32_t cross =
             slots_tick<N, kPaced>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
         if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
-            const bool rank = live && cross;
-            const int k = slots_rank_park<N>(sl, cross, rank, L, smem, ucol, icol, pbase, nfin,
-                                             winner, row);
-            if (rank) {
-                nfin += k;
-                steps += (unsigned long long)k * (t + 1 - t0);
+            if constexpr (kRankPark) {
+                const bool rank = live && cross;
+                const int k = slots_rank_park<N>(sl, cross, rank, L, smem, ucol, icol, pbase,
+                                                 nfin, winner, row);
+                if (rank) {
+                    nfin += k;
+                    steps += (unsigned long long)k * (t + 1 - t0);
+                }
+            } else {
+                if (live && cross) {
+                    const int k =
+                        slots_rank<N>(sl, cross, L, smem, ucol, icol, pbase, nfin, winner, row);
+                    nfin += k;
+                    steps += (unsigned long long)k * (t + 1 - t0);
+                }
+                slots_park<N>(sl, cross);
             }
         }
         if (live && (nfin >= stop_after || t + 1 - t0 >= kTickLimit)) {
