@@ -68,7 +68,7 @@ __device__ void run_prefix_lane(const ReqDesc& rq, char* smem, uint32_t ucol, ui
             break;
         }
         uint32_t cross =
-            slots_tick<N, true>(sl, smem, ucol, pbase, rq.rc.L, t, rq.prefix_sim, rq.request, k0,
+            slots_tick<N, kPaceInline>(sl, smem, ucol, pbase, rq.rc.L, t, rq.prefix_sim, rq.request, k0,
                                 k1);
         t += 1;
         if (cross) {

@@ -53,9 +53,9 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
         // re-read the start state from LDS each generation rather than
         // keeping 3N registers live across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced, false>(smem, ucol, icol, pbase, rq.rc.L, d0, s0, id0, rq.t0,
-                                         live, sim, rq.request, k0, k1, rq.stop_after, nullptr,
-                                         hist, steps);
+        run_generation<N, kPaced ? kPaceTable : kPaceOff, false>(
+            smem, ucol, icol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim, rq.request, k0, k1,
+            rq.stop_after, nullptr, hist, steps);
     }
     if (lane < N) {
         uint32_t w = hist[lane];
@@ -63,11 +63,11 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
     }
 }
 
-// Waves per SIMD the register allocation aims for: 4 where the body fits in
-// 128 VGPRs without spilling, else 3.
+// Waves per SIMD the register allocation aims for (4: the body fits in 128
+// VGPRs without spilling).
 template <int N, bool kPaced = false>
 constexpr int batch_waves_per_eu() {
-    return (kPaced && N >= 16) ? 3 : 4;
+    return 4;
 }
 
 // Persistent kernel for the work items of one competitor count; up to 4

@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(64) race_trace_kernel(const TraceArgs a) {
     // at most max_rows - 1 <= 2^20 ticks
     while (rows < a.max_rows) {
         const uint32_t cross =
-            slots_tick<N, true>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
+            slots_tick<N, kPaceInline>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
         if (cross) break;
         t += 1;
         slots_restore<N>(sl);

@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(64) race_prefix_kernel(const PrefixArgs a) {
             break;
         }
         uint32_t cross =
-            slots_tick<N, true>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
+            slots_tick<N, kPaceInline>(sl, smem, ucol, kPar, a.rc.L, t, a.sim, a.request, a.k0, a.k1);
         t += 1;
         if (cross) {
             ok = false;

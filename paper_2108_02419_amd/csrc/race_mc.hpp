@@ -12,11 +12,14 @@ namespace bbe {
 constexpr int kWaves = 4;
 constexpr int kBlock = 64 * kWaves;
 
-template <int N>
+// Parameter records: one table for the workgroup, or one per wave in the
+// paced variant (each wave writes its own tick's time terms into them).
+template <int N, bool kPaced = false>
 struct BlockLds {
     static constexpr uint32_t kU = 0;                                      // [wave] u tables
     static constexpr uint32_t kPar = ((kWaves * N * 256 + 1023) / 1024) * 1024;  // records
-    static constexpr uint32_t kWins = kPar + 1024;                        // u32[N]
+    static constexpr uint32_t kParBytes = kPaced ? ((kWaves * N * 32 + 1023) / 1024) * 1024 : 1024;
+    static constexpr uint32_t kWins = kPar + kParBytes;                   // u32[N]
     static constexpr uint32_t kSteps = kWins + 128;                        // u64
     static constexpr uint32_t kInit = kSteps + 16;  // start state: d0, s0 (f32[N]), id0 (u8[N])
     static constexpr uint32_t kIds = kInit + kMaxN * 12;  // [wave] finisher ids, u8[N][64]
@@ -29,34 +32,39 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
     return v;
 }
 
-// Waves per SIMD the register allocation aims for: 4 where the body fits in
-// 128 VGPRs without spilling, else 3 (the paced variant's larger competitor
-// counts, which hold two more prefetched parameters per slot).
+// Waves per SIMD the register allocation aims for (4: the body fits in 128
+// VGPRs without spilling).
 template <int N, bool kPaced = false>
 constexpr int mc_waves_per_eu() {
-    return (kPaced && N >= 16) ? 3 : 4;
+    return 4;
 }
 
 template <int N, bool kPaced>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<N, kPaced>()))) race_mc_kernel(const SimArgs a) {
-    using Lay = BlockLds<N>;
+    using Lay = BlockLds<N, kPaced>;
     __shared__ __attribute__((aligned(1024))) char smem[Lay::kBytes];
     const int wave = threadIdx.x >> 6;
     const int lane = threadIdx.x & 63;
     const uint32_t ucol = Lay::kU + wave * (N * 256) + lane * 4;
     const uint32_t icol = Lay::kIds + wave * (N * 64) + lane;
-    // one record table for the workgroup (every wave simulates the same
-    // race), at a compile-time offset
-    const uint32_t pbase = Lay::kPar;
+    // plain: one record table for the workgroup (every wave simulates the
+    // same race), at a compile-time offset; paced: one table per wave
+    const uint32_t pbase =
+        kPaced ? Lay::kPar + (uint32_t)__builtin_amdgcn_readfirstlane(wave) * (N * 32u)
+               : Lay::kPar;
     uint32_t* s_wins = reinterpret_cast<uint32_t*>(smem + Lay::kWins);
     unsigned long long* s_steps = reinterpret_cast<unsigned long long*>(smem + Lay::kSteps);
 
     float* s_d0 = reinterpret_cast<float*>(smem + Lay::kInit);
     float* s_s0 = s_d0 + kMaxN;
     uint8_t* s_id0 = reinterpret_cast<uint8_t*>(s_s0 + kMaxN);
-    write_params<N>(smem, pbase, a.rc, (int)threadIdx.x);
-    if constexpr (kPaced) write_pace<N>(smem, pbase, a.pace, (int)threadIdx.x);
+    if constexpr (kPaced) {
+        write_params<N>(smem, pbase, a.rc, lane);
+        write_pace<N>(smem, pbase, a.pace, lane);
+    } else {
+        write_params<N>(smem, pbase, a.rc, (int)threadIdx.x);
+    }
     if (threadIdx.x < N) {
         s_wins[threadIdx.x] = 0u;
         s_d0[threadIdx.x] = a.d0[threadIdx.x];
@@ -78,9 +86,9 @@ __global__ void __launch_bounds__(kBlock)
         // re-read the start state from LDS each generation rather than
         // keeping it live (in registers) across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced>(smem, ucol, icol, pbase, L, s_d0, s_s0, s_id0, a.t0, live,
-                          a.sim_begin + (uint32_t)j, a.request, a.k0, a.k1, a.stop_after, row,
-                          s_wins, steps);
+        run_generation<N, kPaced ? kPaceTable : kPaceOff>(
+            smem, ucol, icol, pbase, L, s_d0, s_s0, s_id0, a.t0, live, a.sim_begin + (uint32_t)j,
+            a.request, a.k0, a.k1, a.stop_after, row, s_wins, steps);
     }
 
     steps = wave_sum_u64(steps);

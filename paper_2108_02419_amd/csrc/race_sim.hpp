@@ -24,7 +24,7 @@
 //      greater than d_c (lowest index among equal positions); gap =
 //      fl(d_ahead - d_c), +inf if nobody is ahead;
 //   3. Eq. 1: R = alpha + beta*d (+ gamma*min(t, tau) in the paced
-//      variant); free: S = R*(elo + espan*u); blocked (gap <= theta):
+//      variants); free: S = R*(elo + espan*u); blocked (gap <= theta):
 //      S = R*min(s_c, s_ahead);
 //   4. synchronous update d += S, s = S of the running competitors; a
 //      competitor whose new position reaches L crosses the line;
@@ -66,9 +66,21 @@ __device__ __forceinline__ float parked() {
     return __uint_as_float(0x7FC00000u);
 }
 
+// How slots_tick adds the time term gamma*min(t, tau) of R:
+//   kPaceOff    no time term (gamma = 0 everywhere);
+//   kPaceInline every slot reads its competitor's gamma and tau and forms the
+//               term itself (lanes may be at different ticks);
+//   kPaceTable  all lanes of the wave are at the same tick: lane c forms
+//               competitor c's term once per tick into its record, and every
+//               slot adds it.  The term is the same rounded product either
+//               way, so the three modes agree bit for bit.
+enum Pace : int { kPaceOff = 0, kPaceInline = 1, kPaceTable = 2 };
+
 // Writes the parameter records of a race into a record block: record c =
-// (elo, espan16, alpha, beta, theta, gamma, tau, -) at pbase + 32*c; gamma
-// and tau are written (by the same lane, afterwards) by write_pace.
+// (elo, espan16, alpha, beta, theta, gamma | term, tau, gamma) at
+// pbase + 32*c; the time-term fields are written (by the same lane,
+// afterwards) by write_pace.  Offset 20 holds gamma for kPaceInline and
+// the current tick's term for kPaceTable.
 template <int N>
 __device__ __forceinline__ void write_params(char* smem, uint32_t pbase, const RaceConst& rc,
                                             int lane) {
@@ -86,6 +98,7 @@ __device__ __forceinline__ void write_pace(char* smem, uint32_t pbase, const Rac
         float* rec = reinterpret_cast<float*>(smem + pbase + lane * 32);
         rec[5] = pc.gamma[lane];
         rec[6] = pc.tau[lane];
+        rec[7] = pc.gamma[lane];
     }
 }
 
@@ -107,13 +120,30 @@ __device__ __forceinline__ void slots_reset(Slots<N>& sl, const float* __restric
 // of the draw table (competitor c's draw at ucol + 256*c), `pbase` that of
 // the parameter records.  Returns the bit mask of slots that crossed the
 // line (their position still holds the start-of-tick value; their s holds
-// the step S that took them over).  kPaced adds the time term of R (with
-// gamma = 0 it adds +0, so both variants agree on unpaced races).
-template <int N, bool kPaced = false>
+// the step S that took them over).  kPace selects how the time term of R
+// is added (with gamma = 0 it adds +0, so every mode agrees on unpaced
+// races).
+template <int N, Pace kPace = kPaceOff>
 __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_t ucol,
                                                uint32_t pbase, float L, uint32_t t,
                                                uint32_t sim, uint32_t request, uint32_t k0,
                                                uint32_t k1) {
+    const float tf = (float)t;
+    if constexpr (kPace == kPaceTable) {
+        // this tick's term of competitor c, formed by lane c (t is the same
+        // in every lane) into its record for the wave's slots to add
+        const uint32_t lane = __lane_id();
+        if (lane < (uint32_t)N) {
+            const uint32_t r = pbase + 32u * lane;
+            const float2 tg = *reinterpret_cast<const float2*>(smem + r + 24u);  // (tau, gamma)
+            lds_st_f32(smem, r + 20u, tg.y * fminf(tf, tg.x));
+        }
+        // the wave's LDS operations complete in order; keep the compiler
+        // from moving the slots' reads above this store
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    }
     // 1. draws, competitor order, into this lane's column
 #pragma unroll
     for (int b = 0; b < (N + 7) / 8; ++b) {
@@ -139,17 +169,20 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
     constexpr int kPf = 4;
     float pu[N], pth[N], pga[N], pta[N];
     float4 pp[N];
-    const float tf = (float)t;
 #pragma unroll
     for (int k = N - 1; k >= 0 && k >= N - kPf; --k) {
         const uint32_t rec = sl.rec[k];
         pu[k] = lds_f32(smem, ubias + (rec << 3));
         pp[k] = *reinterpret_cast<const float4*>(smem + rec);
-        if constexpr (kPaced) {
+        if constexpr (kPace == kPaceInline) {
             const float4 q = *reinterpret_cast<const float4*>(smem + rec + 16);
             pth[k] = q.x;
             pga[k] = q.y;
             pta[k] = q.z;
+        } else if constexpr (kPace == kPaceTable) {
+            const float2 q = *reinterpret_cast<const float2*>(smem + rec + 16);
+            pth[k] = q.x;
+            pga[k] = q.y;  // the term itself
         } else {
             pth[k] = lds_f32(smem, rec + 16);
         }
@@ -163,11 +196,15 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
             const uint32_t rec = sl.rec[k - kPf];
             pu[k - kPf] = lds_f32(smem, ubias + (rec << 3));
             pp[k - kPf] = *reinterpret_cast<const float4*>(smem + rec);
-            if constexpr (kPaced) {
+            if constexpr (kPace == kPaceInline) {
                 const float4 q = *reinterpret_cast<const float4*>(smem + rec + 16);
                 pth[k - kPf] = q.x;
                 pga[k - kPf] = q.y;
                 pta[k - kPf] = q.z;
+            } else if constexpr (kPace == kPaceTable) {
+                const float2 q = *reinterpret_cast<const float2*>(smem + rec + 16);
+                pth[k - kPf] = q.x;
+                pga[k - kPf] = q.y;
             } else {
                 pth[k - kPf] = lds_f32(smem, rec + 16);
             }
@@ -180,7 +217,8 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
         // Eq. 1
         const float4 p = pp[k];
         float R = p.z + p.w * d;
-        if constexpr (kPaced) R = R + pga[k] * fminf(tf, pta[k]);
+        if constexpr (kPace == kPaceInline) R = R + pga[k] * fminf(tf, pta[k]);
+        if constexpr (kPace == kPaceTable) R = R + pga[k];
         float x = p.x + p.y * pu[k];
         // min of two positive steps (ns = 0 only when nobody is ahead)
         float s_min = __uint_as_float(min(__float_as_uint(s), __float_as_uint(ns)));
@@ -380,7 +418,7 @@ __device__ __forceinline__ void slots_restore(Slots<N>& sl) {
 // kRankPark selects slots_rank_park (one pass that ranks and parks) over
 // slots_rank followed by slots_park; the two give the same results, and
 // each kernel takes the one its register allocation does better with.
-template <int N, bool kPaced = false, bool kRankPark = true>
+template <int N, Pace kPace = kPaceOff, bool kRankPark = true>
 __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t icol,
                                                uint32_t pbase,
                                                float L, const float* __restrict__ d0,
@@ -396,7 +434,7 @@ __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32
     int nfin = 0, winner = -1;
     while (__builtin_amdgcn_ballot_w64(live)) {
         const uint32_t cross =
-            slots_tick<N, kPaced>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
+            slots_tick<N, kPace>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
         if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
             if constexpr (kRankPark) {
                 const bool rank = live && cross;
