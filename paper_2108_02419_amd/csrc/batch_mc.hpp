@@ -27,6 +27,14 @@ __device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v
     return v;
 }
 
+// Parked slots stop being stepped 4 at a time once every lane has parked
+// them, for N = 12 .. 17 (from N = 18 on the extra copies of the tick make
+// this kernel spill inside the tick loop).
+template <int N>
+constexpr int batch_skip_step() {
+    return (N >= 12 && N <= 17) ? 4 : 0;
+}
+
 template <int N, bool kPaced>
 __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, char* smem,
                                           uint32_t wbase, int lane, uint32_t k0, uint32_t k1,
@@ -53,7 +61,7 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
         // re-read the start state from LDS each generation rather than
         // keeping 3N registers live across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced ? kPaceTable : kPaceOff, false>(
+        run_generation<N, kPaced ? kPaceTable : kPaceOff, false, batch_skip_step<N>()>(
             smem, ucol, icol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim, rq.request, k0, k1,
             rq.stop_after, nullptr, hist, steps);
     }

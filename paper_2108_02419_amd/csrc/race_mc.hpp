@@ -39,6 +39,14 @@ constexpr int mc_waves_per_eu() {
     return 4;
 }
 
+// Parked slots stop being stepped 4 at a time once every lane has parked
+// them (from N = 12 on; smaller races gain too little for the extra copies
+// of the tick).
+template <int N>
+constexpr int mc_skip_step() {
+    return N >= 12 ? 4 : 0;
+}
+
 template <int N, bool kPaced>
 __global__ void __launch_bounds__(kBlock)
     __attribute__((amdgpu_waves_per_eu(mc_waves_per_eu<N, kPaced>()))) race_mc_kernel(const SimArgs a) {
@@ -86,7 +94,7 @@ __global__ void __launch_bounds__(kBlock)
         // re-read the start state from LDS each generation rather than
         // keeping it live (in registers) across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced ? kPaceTable : kPaceOff>(
+        run_generation<N, kPaced ? kPaceTable : kPaceOff, true, mc_skip_step<N>()>(
             smem, ucol, icol, pbase, L, s_d0, s_s0, s_id0, a.t0, live, a.sim_begin + (uint32_t)j,
             a.request, a.k0, a.k1, a.stop_after, row, s_wins, steps);
     }

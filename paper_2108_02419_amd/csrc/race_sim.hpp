@@ -38,6 +38,8 @@
 
 #include "race_common.hpp"
 
+#include <type_traits>
+
 namespace bbe {
 
 template <int N>
@@ -122,8 +124,10 @@ __device__ __forceinline__ void slots_reset(Slots<N>& sl, const float* __restric
 // line (their position still holds the start-of-tick value; their s holds
 // the step S that took them over).  kPace selects how the time term of R
 // is added (with gamma = 0 it adds +0, so every mode agrees on unpaced
-// races).
-template <int N, Pace kPace = kPaceOff>
+// races).  Only the A lowest slots are stepped: the caller guarantees that
+// slots A .. N-1 are parked in every lane (a parked slot's step changes
+// nothing: it stays parked and is never ahead of anyone).
+template <int N, Pace kPace = kPaceOff, int A = N>
 __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_t ucol,
                                                uint32_t pbase, float L, uint32_t t,
                                                uint32_t sim, uint32_t request, uint32_t k0,
@@ -170,7 +174,7 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
     float pu[N], pth[N], pga[N], pta[N];
     float4 pp[N];
 #pragma unroll
-    for (int k = N - 1; k >= 0 && k >= N - kPf; --k) {
+    for (int k = A - 1; k >= 0 && k >= A - kPf; --k) {
         const uint32_t rec = sl.rec[k];
         pu[k] = lds_f32(smem, ubias + (rec << 3));
         pp[k] = *reinterpret_cast<const float4*>(smem + rec);
@@ -191,7 +195,7 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
     float d_up = __builtin_inff(), s_up = 0.0f;
     uint32_t cross = 0;
 #pragma unroll
-    for (int k = N - 1; k >= 0; --k) {
+    for (int k = A - 1; k >= 0; --k) {
         if (k - kPf >= 0) {
             const uint32_t rec = sl.rec[k - kPf];
             pu[k - kPf] = lds_f32(smem, ubias + (rec << 3));
@@ -249,14 +253,14 @@ __device__ __forceinline__ uint32_t slots_tick(Slots<N>& sl, char* smem, uint32_
 // ucol + 256*j -- and its slot is parked.  The entries are then picked in
 // (fraction, index) order by a selection over those c entries, so the work
 // grows with c^2 for the few finishers of a tick rather than with c*N.
-template <int N>
+template <int N, int A = N>
 __device__ __forceinline__ int slots_rank_park(Slots<N>& sl, uint32_t cross, bool rank, float L,
                                                char* smem, uint32_t ucol, uint32_t icol,
                                                uint32_t pbase, int nfin, int& winner,
                                                uint8_t* __restrict__ row) {
     const int c = __builtin_popcount(cross);
 #pragma unroll
-    for (int k = 0; k < N; ++k)
+    for (int k = 0; k < A; ++k)
         if ((cross >> k) & 1u) {
             if (rank) {
                 const uint32_t j = __builtin_popcount(cross & ((1u << k) - 1u));
@@ -373,11 +377,11 @@ __device__ __forceinline__ void slots_cx(Slots<N>& sl, int k) {
 // One upward pass (k = 0 .. N-2; carries a slot up any distance).  Returns
 // true if the result may still be out of order: each slot is final once the
 // pass has left it, so the pass checks every finished neighbour pair.
-template <int N>
+template <int N, int A = N>
 __device__ __forceinline__ bool slots_pass_up(Slots<N>& sl) {
     bool bad = false;
 #pragma unroll
-    for (int k = 0; k < N - 1; ++k) {
+    for (int k = 0; k < A - 1; ++k) {
         slots_cx<N>(sl, k);
         if (k >= 1)
             bad |= slot_key(sl.d[k - 1], sl.rec[k - 1]) > slot_key(sl.d[k], sl.rec[k]);
@@ -386,13 +390,13 @@ __device__ __forceinline__ bool slots_pass_up(Slots<N>& sl) {
 }
 
 // One downward pass (k = N-2 .. 0; carries a slot down any distance).
-template <int N>
+template <int N, int A = N>
 __device__ __forceinline__ bool slots_pass_down(Slots<N>& sl) {
     bool bad = false;
 #pragma unroll
-    for (int k = N - 2; k >= 0; --k) {
+    for (int k = A - 2; k >= 0; --k) {
         slots_cx<N>(sl, k);
-        if (k + 2 <= N - 1)
+        if (k + 2 <= A - 1)
             bad |= slot_key(sl.d[k + 1], sl.rec[k + 1]) > slot_key(sl.d[k + 2], sl.rec[k + 2]);
     }
     return bad;
@@ -400,12 +404,23 @@ __device__ __forceinline__ bool slots_pass_down(Slots<N>& sl) {
 
 // Step 6 in full: alternate passes until every active lane of the wave is
 // in order (a tick's overtakes need one pass in most lanes, two where a
-// slot moves down by more than one place).
-template <int N>
+// slot moves down by more than one place).  Sorting the A lowest slots
+// suffices when slots A .. N-1 are parked in every lane: the order among
+// parked slots is never used.
+template <int N, int A = N>
 __device__ __forceinline__ void slots_restore(Slots<N>& sl) {
     for (;;) {
-        if (!__builtin_amdgcn_ballot_w64(slots_pass_up<N>(sl))) break;
-        if (!__builtin_amdgcn_ballot_w64(slots_pass_down<N>(sl))) break;
+        if (!__builtin_amdgcn_ballot_w64(slots_pass_up<N, A>(sl))) break;
+        if (!__builtin_amdgcn_ballot_w64(slots_pass_down<N, A>(sl))) break;
+    }
+}
+
+// Runs f(std::integral_constant<int, A>) for A = N, N - kStep, ... (A >=
+// kStep) one after the other for as long as f returns true.
+template <int A, int kStep, class F>
+__device__ __forceinline__ void run_phases(F& f) {
+    if (f(std::integral_constant<int, A>{})) {
+        if constexpr (A - kStep >= kStep) run_phases<A - kStep, kStep>(f);
     }
 }
 
@@ -418,7 +433,11 @@ __device__ __forceinline__ void slots_restore(Slots<N>& sl) {
 // kRankPark selects slots_rank_park (one pass that ranks and parks) over
 // slots_rank followed by slots_park; the two give the same results, and
 // each kernel takes the one its register allocation does better with.
-template <int N, Pace kPace = kPaceOff, bool kRankPark = true>
+// kSkipStep > 0 stops stepping and sorting the top slots once they are
+// parked in every lane, kSkipStep slots at a time (a copy of the tick per
+// active count): late in a generation most lanes have parked most of their
+// competitors.
+template <int N, Pace kPace = kPaceOff, bool kRankPark = true, int kSkipStep = 0>
 __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32_t icol,
                                                uint32_t pbase,
                                                float L, const float* __restrict__ d0,
@@ -432,37 +451,96 @@ __device__ __forceinline__ void run_generation(char* smem, uint32_t ucol, uint32
     slots_reset<N>(sl, d0, s0, id0, pbase);
     uint32_t t = t0;
     int nfin = 0, winner = -1;
-    while (__builtin_amdgcn_ballot_w64(live)) {
-        const uint32_t cross =
-            slots_tick<N, kPace>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
-        if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
-            if constexpr (kRankPark) {
-                const bool rank = live && cross;
-                const int k = slots_rank_park<N>(sl, cross, rank, L, smem, ucol, icol, pbase,
-                                                 nfin, winner, row);
-                if (rank) {
-                    nfin += k;
-                    steps += (unsigned long long)k * (t + 1 - t0);
+    // One phase steps the A lowest slots (slots A .. N-1 are parked in every
+    // lane) until the generation ends (returns false) or the next kSkipStep
+    // slots down are parked in every lane too (returns true).
+    auto phase = [&](auto act) -> bool {
+        constexpr int A = decltype(act)::value;
+        while (__builtin_amdgcn_ballot_w64(live)) {
+            // the Philox products that depend on the simulation index only
+            // are recomputed each tick rather than held (or spilled) across
+            // the phases' loops
+            uint32_t sim_t = sim;
+            __asm__ volatile("" : "+v"(sim_t));
+            const uint32_t cross =
+                slots_tick<N, kPace, A>(sl, smem, ucol, pbase, L, t, sim_t, request, k0, k1);
+            const bool any = __builtin_amdgcn_ballot_w64(cross != 0u) != 0;
+            if (any) {
+                if constexpr (kRankPark) {
+                    const bool rank = live && cross;
+                    const int k = slots_rank_park<N, A>(sl, cross, rank, L, smem, ucol, icol,
+                                                        pbase, nfin, winner, row);
+                    if (rank) {
+                        nfin += k;
+                        steps += (unsigned long long)k * (t + 1 - t0);
+                    }
+                } else {
+                    if (live && cross) {
+                        const int k = slots_rank<N>(sl, cross, L, smem, ucol, icol, pbase, nfin,
+                                                    winner, row);
+                        nfin += k;
+                        steps += (unsigned long long)k * (t + 1 - t0);
+                    }
+                    slots_park<N>(sl, cross);
                 }
-            } else {
-                if (live && cross) {
-                    const int k =
-                        slots_rank<N>(sl, cross, L, smem, ucol, icol, pbase, nfin, winner, row);
-                    nfin += k;
-                    steps += (unsigned long long)k * (t + 1 - t0);
-                }
-                slots_park<N>(sl, cross);
+            }
+            if (live && (nfin >= stop_after || t + 1 - t0 >= kTickLimit)) {
+                if (winner >= 0) atomicAdd(&hist[winner], 1u);
+                if (row)
+                    for (int r = nfin; r < N; ++r) row[r] = 0xFF;
+                steps += (unsigned long long)(N - nfin) * (t + 1 - t0);
+                live = false;
+            }
+            t += 1;
+            slots_restore<N, A>(sl);
+            if constexpr (kSkipStep > 0 && A - kSkipStep >= kSkipStep) {
+                // sorted again, so a lane's parked slots are its top ones:
+                // the next kSkipStep slots down are parked everywhere iff the
+                // lowest of them is
+                if (any && !__builtin_amdgcn_ballot_w64(__float_as_uint(sl.d[A - kSkipStep]) !=
+                                                        __float_as_uint(parked())))
+                    return true;
             }
         }
-        if (live && (nfin >= stop_after || t + 1 - t0 >= kTickLimit)) {
-            if (winner >= 0) atomicAdd(&hist[winner], 1u);
-            if (row)
-                for (int r = nfin; r < N; ++r) row[r] = 0xFF;
-            steps += (unsigned long long)(N - nfin) * (t + 1 - t0);
-            live = false;
+        return false;
+    };
+    if constexpr (kSkipStep > 0) {
+        run_phases<N, kSkipStep>(phase);
+    } else {
+        // the same tick over all N slots, written out as a plain loop (the
+        // batch kernel's register allocation is tuned on this form)
+        while (__builtin_amdgcn_ballot_w64(live)) {
+            const uint32_t cross =
+                slots_tick<N, kPace>(sl, smem, ucol, pbase, L, t, sim, request, k0, k1);
+            if (__builtin_amdgcn_ballot_w64(cross != 0u)) {
+                if constexpr (kRankPark) {
+                    const bool rank = live && cross;
+                    const int k = slots_rank_park<N>(sl, cross, rank, L, smem, ucol, icol,
+                                                     pbase, nfin, winner, row);
+                    if (rank) {
+                        nfin += k;
+                        steps += (unsigned long long)k * (t + 1 - t0);
+                    }
+                } else {
+                    if (live && cross) {
+                        const int k = slots_rank<N>(sl, cross, L, smem, ucol, icol, pbase, nfin,
+                                                    winner, row);
+                        nfin += k;
+                        steps += (unsigned long long)k * (t + 1 - t0);
+                    }
+                    slots_park<N>(sl, cross);
+                }
+            }
+            if (live && (nfin >= stop_after || t + 1 - t0 >= kTickLimit)) {
+                if (winner >= 0) atomicAdd(&hist[winner], 1u);
+                if (row)
+                    for (int r = nfin; r < N; ++r) row[r] = 0xFF;
+                steps += (unsigned long long)(N - nfin) * (t + 1 - t0);
+                live = false;
+            }
+            t += 1;
+            slots_restore<N>(sl);
         }
-        t += 1;
-        slots_restore<N>(sl);
     }
 }
 
