@@ -62,27 +62,39 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def profiled_traffic():
-    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy-probe
-    factors) from the committed profile, or None if the profile is missing or
-    was taken on other kernel sources."""
+def profiled_values() -> dict:
+    """Figures of the committed profile of the dominant kernel, keyed by
+    their header names (kernel_sources_sha256, traffic_bytes_per_launch,
+    valu_busy_pct, ...), or {} if the profile is missing or was taken on
+    other kernel sources."""
     try:
         with open(PROFILE) as f:
             text = f.read()
     except OSError:
-        return None
+        return {}
     vals = {}
     for line in text.splitlines():
         line = line.strip().strip("`")
-        for key in ("kernel_sources_sha256:", "traffic_bytes_per_launch:"):
-            if line.startswith(key):
-                vals[key] = line[len(key):].strip()
-    if vals.get("kernel_sources_sha256:") != kernel_sources_sha256():
-        return None
+        key, sep, val = line.partition(":")
+        if sep and key and " " not in key and key == key.lower() and val.strip():
+            vals.setdefault(key, val.strip())
+    if vals.get("kernel_sources_sha256") != kernel_sources_sha256():
+        return {}
+    return vals
+
+
+def profiled_float(name: str):
     try:
-        return float(vals["traffic_bytes_per_launch:"])
+        return float(profiled_values()[name])
     except (KeyError, ValueError):
         return None
+
+
+def profiled_traffic():
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by the copy-probe
+    factors) from the committed profile, or None if the profile is missing or
+    was taken on other kernel sources."""
+    return profiled_float("traffic_bytes_per_launch")
 
 
 def cpu_baseline(c, target_s: float = 12.0):
@@ -291,7 +303,10 @@ def main() -> int:
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_PEAK_OPS / 1e12,
                      "unit": "TOP/s", "frac": achieved / VALU_PEAK_OPS,
                      "traffic": profiled_traffic(),
-                     "instr_per_competitor_step": ALGO_OPS_PER_COMPETITOR_STEP},
+                     "instr_per_competitor_step": ALGO_OPS_PER_COMPETITOR_STEP,
+                     # rocprofv3 counters of the same kernel sources (null if stale)
+                     "valu_busy_pct": profiled_float("valu_busy_pct"),
+                     "valu_lane_activity_pct": profiled_float("valu_lane_activity_pct")},
     }
     if not args.no_batch:
         line["batch"] = batch_leg(args.batch_steps)
