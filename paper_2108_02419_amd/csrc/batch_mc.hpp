@@ -28,11 +28,17 @@ __device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v
 }
 
 // Parked slots stop being stepped 4 at a time once every lane has parked
-// them, for N = 12 .. 17 (from N = 18 on the extra copies of the tick make
-// this kernel spill inside the tick loop).
-template <int N>
+// them, from N = 12 on.  From N = 18 on, the copies of the tick fit in the
+// registers only with ranking and parking in one pass (slots_rank_park);
+// the paced variant spills even so and keeps N = 12 .. 17.
+template <int N, bool kPaced>
 constexpr int batch_skip_step() {
-    return (N >= 12 && N <= 17) ? 4 : 0;
+    return (N >= 12 && (!kPaced || N <= 17)) ? 4 : 0;
+}
+
+template <int N, bool kPaced>
+constexpr bool batch_rank_park() {
+    return !kPaced && N >= 18;
 }
 
 template <int N, bool kPaced>
@@ -61,7 +67,8 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
         // re-read the start state from LDS each generation rather than
         // keeping 3N registers live across the loop
         __asm__ volatile("" ::: "memory");
-        run_generation<N, kPaced ? kPaceTable : kPaceOff, false, batch_skip_step<N>()>(
+        run_generation<N, kPaced ? kPaceTable : kPaceOff, batch_rank_park<N, kPaced>(),
+                       batch_skip_step<N, kPaced>()>(
             smem, ucol, icol, pbase, rq.rc.L, d0, s0, id0, rq.t0, live, sim, rq.request, k0, k1,
             rq.stop_after, nullptr, hist, steps);
     }
