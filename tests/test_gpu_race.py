@@ -178,3 +178,22 @@ def test_full_size_n20_launch(torch, orc):
     p = api.win_probs(counts["wins"])
     torch.cuda.synchronize()
     assert abs(p.sum().item() - 1.0) <= 1e-15
+
+
+@pytest.mark.parametrize("n", [12, 17, 20])
+def test_fast_group_parks_early(torch, orc, n):
+    """A fast group finishes long before a slow one in every simulation, so
+    the top slots are parked in every lane for most of the race and the
+    kernel steps and sorts only the lower slots from then on; the results
+    must not change (orders, wins and steps bit-exact), also when lanes stop
+    early (stop_after) and for a tied deterministic fast group."""
+    rng = np.random.default_rng(400 + n)
+    comp = inputs.competitor_params(rng, n)
+    fast = rng.choice(n, size=n // 2, replace=False)
+    comp[fast, 0] *= 3.0
+    comp[fast, 1] *= 3.0
+    _compare(torch, orc, comp, 2000.0, 700 + 13 * n, seed=n, request=3)
+    _compare(torch, orc, comp, 2000.0, 300, seed=n, request=4, stop_after=n - 2)
+    tied = comp.copy()
+    tied[fast] = [12.0, 12.0, 1.0, 0.0, 2.0]
+    _compare(torch, orc, tied, 2000.0, 200, seed=n, request=5)
