@@ -541,12 +541,16 @@ def gated_leg(states: int = 200_000, label_sims: int = 1000, epochs: int = 60,
             "mc_queries_per_s": loop["mc_queries_per_s"],
             "system_speedup": loop["system_speedup"],
             "answer_err_max": loop["answer_err"]["max"],
+            "answer_err": loop["answer_err"],
             "mc_err_max": loop["mc_err"]["max"],
+            "mc_err": loop["mc_err"],
             "served_frac": loop["served_frac"],
             "surrogate_raw_speedup": loop["speedup"],
             "surrogate_raw_err": loop["surrogate_err"],
             "heldout": {"tv_mean": res["surrogate_vs_judge"]["tv_mean"],
                         "max_abs": res["surrogate_vs_judge"]["max_abs"],
+                        "mean_abs": res["surrogate_vs_judge"].get("mean_abs"),
+                        "p999_abs": res["surrogate_vs_judge"].get("p999"),
                         "gate": res["gate"]},
             "setup_s": setup_s}
 

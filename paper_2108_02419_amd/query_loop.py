@@ -151,9 +151,12 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
                 system_queries_per_s=sys_qps, system_speedup=sys_qps / mc_qps,
                 flagged_rounds=n_flag, served_frac=1.0 - n_flag / max(1, len(rounds)),
                 surrogate_err=dict(max=float(sur_err.max()), mean=float(sur_err.mean()),
-                                   p99=float(np.quantile(sur_err, 0.99))),
-                answer_err=dict(max=float(ans_err.max()), mean=float(ans_err.mean())),
-                mc_err=dict(max=float(mc_err.max()), mean=float(mc_err.mean())),
+                                   p99=float(np.quantile(sur_err, 0.99)),
+                                   p999=float(np.quantile(sur_err, 0.999))),
+                answer_err=dict(max=float(ans_err.max()), mean=float(ans_err.mean()),
+                                p999=float(np.quantile(ans_err, 0.999))),
+                mc_err=dict(max=float(mc_err.max()), mean=float(mc_err.mean()),
+                            p999=float(np.quantile(mc_err, 0.999))),
                 per_round=rounds)
 
 
