@@ -430,7 +430,10 @@ int bbe_mlp_forward(const bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
  * (device float [batch][20], each row summing to 1 over its valid slots)
  * into loss (device float[1], overwritten), and its gradient into grad
  * (device float[BBE_MLP_NPARAMS], overwritten; NULL = the network's own
- * gradient buffer, used by bbe_mlp_adam_step with grad = NULL).            */
+ * gradient buffer, used by bbe_mlp_adam_step with grad = NULL).  The
+ * gradient is summed over the rows in a fixed order: the same inputs give
+ * the same bits on every call (the loss is summed with atomics and may
+ * differ in its last bits).                                                */
 int bbe_mlp_loss_grad(bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
                       const float *target, int batch, float *loss, float *grad, void *stream);
 

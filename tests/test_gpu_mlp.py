@@ -75,6 +75,31 @@ def test_gradients_match_reference(torch):
         assert err <= 1e-3, (name, err)
 
 
+def test_gradients_are_reproducible_over_several_row_chunks(torch):
+    """1000 rows (four 256-row chunks of the weight-gradient kernel): the
+    gradient matches the reference and two calls give the same bits."""
+    rng = np.random.default_rng(5)
+    params = inputs.surrogate_init(4)
+    B = 1000
+    X, n, T = _features(rng, B)
+    announce(f"mlp gradients B={B}, twice")
+    net = _bbe.Mlp(params, max_batch=1024)
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    grads = []
+    for _ in range(2):
+        grad = torch.empty(_bbe.MLP_NPARAMS, dtype=torch.float32, device="cuda")
+        net.loss_grad(_bits(torch, X), torch.tensor(n, device="cuda"),
+                      torch.tensor(T, device="cuda"), loss, grad)
+        torch.cuda.synchronize()
+        grads.append(grad.cpu().numpy())
+    np.testing.assert_array_equal(grads[0], grads[1])
+    _, g_ref = ref.loss_and_grad(params.astype(np.float64), X, n, T)
+    G, R = ref.unpack(grads[0].astype(np.float64)), ref.unpack(g_ref)
+    for name in G:
+        err = np.linalg.norm(G[name] - R[name]) / max(np.linalg.norm(R[name]), 1e-30)
+        assert err <= 1e-3, (name, err)
+
+
 def test_adam_matches_reference(torch):
     rng = np.random.default_rng(2)
     params = inputs.surrogate_init(4)
