@@ -22,6 +22,7 @@ struct bbe_mlp {
     uint16_t *dz4 = nullptr, *dz3 = nullptr, *dz2 = nullptr, *dz1 = nullptr;
     bbe::WgradTile* tiles = nullptr;
     int n_tiles = 0;
+    float* wpart = nullptr;  // [chunks of kWgRows rows][kNParams], when max_batch > kWgRows
 };
 
 namespace {
@@ -33,7 +34,7 @@ void destroy(bbe_mlp* m) {
     if (m->params) (void)hipDeviceSynchronize();
     void* ptrs[] = {m->params, m->m,   m->v,   m->grad, m->w1,  m->w2,  m->w3,  m->w4,
                     m->w2t,    m->w3t, m->w4t, m->h1,   m->h2,  m->h3,  m->dz4, m->dz3,
-                    m->dz2,    m->dz1, m->tiles};
+                    m->dz2,    m->dz1, m->tiles, m->wpart};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete m;
@@ -120,6 +121,8 @@ BBE_API int bbe_mlp_create(const float* params, int max_batch, bbe_mlp** out) {
             for (int k0 = 0; k0 < ks[l]; k0 += 64) tiles.push_back({l, n0, k0, 0});
     m->n_tiles = (int)tiles.size();
     okk = okk && alloc(&m->tiles, tiles.size());
+    const size_t chunks = (B + bbe::kWgRows - 1) / bbe::kWgRows;
+    if (chunks > 1) okk = okk && alloc(&m->wpart, chunks * bbe::kNParams);
     if (!okk) {
         destroy(m);
         return fail(BBE_ENOMEM, "device allocation of the network failed");
@@ -242,13 +245,15 @@ BBE_API int bbe_mlp_loss_grad(bbe_mlp* m, const uint16_t* x, const int32_t* n_va
     bbe::MlpWgradArgs w;
     w.B = batch;
     w.tiles = m->tiles;
-    w.layers[0] = {m->dz1, bbe::kHid, x, bbe::kIn, bbe::kHid, g + bbe::kOffW1, g + bbe::kOffB1};
+    w.layers[0] = {m->dz1, bbe::kHid, x, bbe::kIn, bbe::kHid, g + bbe::kOffW1, g + bbe::kOffB1,
+                   bbe::kOffW1};
     w.layers[1] = {m->dz2, bbe::kHid, m->h1, bbe::kHid, bbe::kHid, g + bbe::kOffW2,
-                   g + bbe::kOffB2};
+                   g + bbe::kOffB2, bbe::kOffW2};
     w.layers[2] = {m->dz3, bbe::kHid, m->h2, bbe::kHid, bbe::kHid, g + bbe::kOffW3,
-                   g + bbe::kOffB3};
+                   g + bbe::kOffB3, bbe::kOffW3};
     w.layers[3] = {m->dz4, bbe::kOutP, m->h3, bbe::kHid, bbe::kOut, g + bbe::kOffW4,
-                   g + bbe::kOffB4};
+                   g + bbe::kOffB4, bbe::kOffW4};
+    w.part = m->wpart;
     if (e == hipSuccess) e = bbe::launch_mlp_wgrad(w, m->n_tiles, s);
     if (e != hipSuccess) return hip_fail(e, "launching the backward pass");
     return ok();

@@ -59,7 +59,11 @@ struct LayerGrad {
     int n_rows;          // outputs of the layer
     float* gw;           // [n_rows][K]
     float* gb;           // [n_rows]
+    int woff;            // offset of gw in the packed parameter vector
 };
+
+// Rows of the batch per weight-gradient work item.
+constexpr int kWgRows = 256;
 
 struct WgradTile {
     int layer, n0, k0, pad;
@@ -69,6 +73,9 @@ struct MlpWgradArgs {
     int B;
     LayerGrad layers[4];
     const WgradTile* tiles;
+    // partial weight gradients, one packed parameter vector per chunk of
+    // kWgRows rows (needed when B > kWgRows); summed in chunk order
+    float* part;
 };
 
 struct MlpAdamArgs {

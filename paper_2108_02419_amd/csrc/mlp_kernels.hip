@@ -232,12 +232,12 @@ __global__ void __launch_bounds__(256) mlp_bwd_data_kernel(const MlpBwdArgs a) {
 }
 
 // Weight gradients dW[n][k] = sum over the batch rows of dz[r][n] * h[r][k].
-// One workgroup: a 64 (n) x 64 (k) tile of one layer; it walks the batch in
-// chunks of kWgRows rows, in order, accumulating in the MFMA registers, and
-// stores the tile once -- no atomics, so the gradient (and training) is the
-// same bit for bit from run to run.  Both operands of a chunk are staged
-// transposed in LDS so that fragments are contiguous.
-constexpr int kWgRows = 256;
+// One workgroup: a 64 (n) x 64 (k) tile of one layer over one chunk of
+// kWgRows rows (blockIdx.y); it stores its tile once -- into the gradient
+// itself when the batch is one chunk, else into that chunk's partial
+// vector, which mlp_wreduce_kernel sums in chunk order.  No atomics, so the
+// gradient (and training) is the same bit for bit from run to run.  Both
+// operands are staged transposed in LDS so that fragments are contiguous.
 constexpr int kWgS = kWgRows + 8;
 
 __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const MlpWgradArgs a) {
@@ -245,41 +245,58 @@ __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const MlpWgradArgs a) {
     __shared__ __attribute__((aligned(16))) uint16_t th[64 * kWgS];  // [k][r]
     const WgradTile t = a.tiles[blockIdx.x];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int r0 = blockIdx.y * kWgRows;
     const LayerGrad& L = a.layers[t.layer];
+    // stage: element (r, n) of dz -> tz[n][r]; (r, k) of h -> th[k][r]
+    for (int i = threadIdx.x; i < kWgRows * 64; i += blockDim.x) {
+        int r = i >> 6, c = i & 63;
+        int row = r0 + r;
+        uint16_t z = 0, h = 0;
+        if (row < a.B) {
+            if (t.n0 + c < L.n_rows) z = L.dz[(size_t)row * L.dz_stride + t.n0 + c];
+            if (t.k0 + c < L.K) h = L.h[(size_t)row * L.K + t.k0 + c];
+        }
+        tz[c * kWgS + r] = z;
+        th[c * kWgS + r] = h;
+    }
+    __syncthreads();
     // wave w: n rows [16w, 16w+16) of the tile, all 64 k columns
     floatx4 acc[4];
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) acc[cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-    for (int r0 = 0; r0 < a.B; r0 += kWgRows) {
-        __syncthreads();  // the previous chunk's fragments have been read
-        // stage: element (r, n) of dz -> tz[n][r]; (r, k) of h -> th[k][r]
-        for (int i = threadIdx.x; i < kWgRows * 64; i += blockDim.x) {
-            int r = i >> 6, c = i & 63;
-            int row = r0 + r;
-            uint16_t z = 0, h = 0;
-            if (row < a.B) {
-                if (t.n0 + c < L.n_rows) z = L.dz[(size_t)row * L.dz_stride + t.n0 + c];
-                if (t.k0 + c < L.K) h = L.h[(size_t)row * L.K + t.k0 + c];
-            }
-            tz[c * kWgS + r] = z;
-            th[c * kWgS + r] = h;
-        }
-        __syncthreads();
-        for (int k0 = 0; k0 < kWgRows; k0 += 32) {
-            bf16x8 fa = frag_lds(tz, kWgS, wave * 16, k0, lane);
+    for (int k0 = 0; k0 < kWgRows; k0 += 32) {
+        bf16x8 fa = frag_lds(tz, kWgS, wave * 16, k0, lane);
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                acc[cb] = mfma(fa, frag_lds(th, kWgS, cb * 16, k0, lane), acc[cb]);
-        }
+        for (int cb = 0; cb < 4; ++cb) acc[cb] = mfma(fa, frag_lds(th, kWgS, cb * 16, k0, lane), acc[cb]);
     }
+    float* out = gridDim.y == 1 ? L.gw : a.part + (size_t)blockIdx.y * kNParams + L.woff;
 #pragma unroll
     for (int cb = 0; cb < 4; ++cb) {
         const int k = t.k0 + cb * 16 + (lane & 15);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const int n = t.n0 + wave * 16 + 4 * (lane >> 4) + i;
-            if (n < L.n_rows && k < L.K) L.gw[(size_t)n * L.K + k] = acc[cb][i];
+            if (n < L.n_rows && k < L.K) out[(size_t)n * L.K + k] = acc[cb][i];
         }
+    }
+}
+
+// Sum of the per-chunk partial weight gradients, chunk 0 first: one thread
+// per weight of the four layers.
+__global__ void __launch_bounds__(256) mlp_wreduce_kernel(const MlpWgradArgs a, int n_chunks) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        const LayerGrad& L = a.layers[l];
+        const int size = L.n_rows * L.K;
+        if (i < size) {
+            const float* p = a.part + L.woff + i;
+            float s = p[0];
+            for (int c = 1; c < n_chunks; ++c) s += p[(size_t)c * kNParams];
+            L.gw[i] = s;
+            return;
+        }
+        i -= size;
     }
 }
 
@@ -408,9 +425,16 @@ hipError_t launch_mlp_bwd_data(const MlpBwdArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_mlp_wgrad(const MlpWgradArgs& a, int n_tiles, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(n_tiles), dim3(256), 0, s, a);
+    const int n_chunks = (a.B + kWgRows - 1) / kWgRows;
+    hipLaunchKernelGGL(mlp_wgrad_kernel, dim3(n_tiles, n_chunks), dim3(256), 0, s, a);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if (n_chunks > 1) {
+        constexpr int kWeights = kHid * kIn + 2 * kHid * kHid + kOut * kHid;
+        hipLaunchKernelGGL(mlp_wreduce_kernel, dim3((kWeights + 255) / 256), dim3(256), 0, s, a,
+                           n_chunks);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(mlp_bgrad_kernel, dim3(kHid / 64, 4), dim3(256), 0, s, a);
     return hipGetLastError();
 }
