@@ -301,20 +301,27 @@ __global__ void __launch_bounds__(256) mlp_wreduce_kernel(const MlpWgradArgs a, 
 }
 
 // Bias gradients: db[n] = sum_r dz[r][n]; one workgroup per 64 columns of a
-// layer, rows strided over the four waves.
-__global__ void __launch_bounds__(256) mlp_bgrad_kernel(const MlpWgradArgs a) {
-    __shared__ float part[4][64];
+// layer, rows strided over its kBgWaves waves, whose partial sums are added
+// in wave order (fixed, so the result is the same on every call).
+constexpr int kBgWaves = 16;
+
+__global__ void __launch_bounds__(64 * kBgWaves) mlp_bgrad_kernel(const MlpWgradArgs a) {
+    __shared__ float part[kBgWaves][64];
     const int layer = blockIdx.y;
     const LayerGrad& L = a.layers[layer];
-    const int n = blockIdx.x * 64 + (threadIdx.x & 63);
+    const int lane = threadIdx.x & 63;
+    const int n = blockIdx.x * 64 + lane;
     const int w = threadIdx.x >> 6;
     float s = 0.0f;
     if (n < L.n_rows)
-        for (int r = w; r < a.B; r += 4) s += from_bf16(L.dz[(size_t)r * L.dz_stride + n]);
-    part[w][threadIdx.x & 63] = s;
+        for (int r = w; r < a.B; r += kBgWaves) s += from_bf16(L.dz[(size_t)r * L.dz_stride + n]);
+    part[w][lane] = s;
     __syncthreads();
-    if (w == 0 && n < L.n_rows)
-        L.gb[n] = (part[0][threadIdx.x] + part[1][threadIdx.x]) + (part[2][threadIdx.x] + part[3][threadIdx.x]);
+    if (w == 0 && n < L.n_rows) {
+        float t = part[0][lane];
+        for (int j = 1; j < kBgWaves; ++j) t += part[j][lane];
+        L.gb[n] = t;
+    }
 }
 
 // Adam on the float32 master parameters (optional) and refresh of the
@@ -435,7 +442,7 @@ hipError_t launch_mlp_wgrad(const MlpWgradArgs& a, int n_tiles, hipStream_t s) {
                            n_chunks);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(mlp_bgrad_kernel, dim3(kHid / 64, 4), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(mlp_bgrad_kernel, dim3(kHid / 64, 4), dim3(64 * kBgWaves), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_mlp_adam(const MlpAdamArgs& a, hipStream_t s) {
