@@ -108,6 +108,56 @@ def loss_and_grad(params, X, n_valid, target, bf16_on=True):
     return loss, pack(g)
 
 
+# ---------------------------------------------------------------------------
+# Per-element bounds for checking one layer of a float32-accumulating
+# implementation on its own inputs.
+#
+# A sum of m terms evaluated in float32 in any order, each addition one
+# rounding, differs from the exact sum by at most gamma_m * sum|t| with
+# gamma_m = m*u / (1 - m*u) (Higham, "Accuracy and Stability of Numerical
+# Algorithms", 2nd ed., Lemma 3.1 and Eq. 3.5).  u is taken as 2^-23, one
+# unit in the last place rather than half of one, so that adders that
+# truncate are covered too.  Products of two bfloat16 values are exact in
+# float32 (8 + 8 significant bits), so the sum is the only error source.
+# The float64 evaluation of the exact sum adds at most m * 2^-53 * sum|t|,
+# which is added to the bound.
+# ---------------------------------------------------------------------------
+U_F32 = 2.0 ** -23
+
+
+def accumulation_bound(abs_sum, m):
+    """Bound on |float32 sum - exact sum| for m terms with sum|t| = abs_sum."""
+    m = float(m)
+    g = m * U_F32 / (1.0 - m * U_F32) + m * 2.0 ** -53
+    return g * np.asarray(abs_sum, dtype=np.float64)
+
+
+def dense_with_bound(h, W, b=None):
+    """Pre-activation h @ bf16(W)^T (+ b) in float64 and the bound on the
+    error of computing it with float32 accumulation (the bias, when given,
+    is one more term of the sum).  h must already be bfloat16 values."""
+    Wb = bf16(W)
+    h = np.asarray(h, dtype=np.float64)
+    a = h @ Wb.T
+    abs_sum = np.abs(h) @ np.abs(Wb).T
+    m = h.shape[1]
+    if b is not None:
+        a = a + np.asarray(b, dtype=np.float64)
+        abs_sum = abs_sum + np.abs(np.asarray(b, dtype=np.float64))
+        m += 1
+    return a, accumulation_bound(abs_sum, m)
+
+
+def bf16_interval(a, e, relu=False):
+    """The bfloat16 values that rounding any float in [a - e, a + e] (after
+    ReLU when relu=True) can give lie in the returned [lo, hi]: rounding to
+    nearest and ReLU are both non-decreasing."""
+    lo, hi = np.asarray(a) - e, np.asarray(a) + e
+    if relu:
+        lo, hi = np.maximum(lo, 0.0), np.maximum(hi, 0.0)
+    return bf16(lo), bf16(hi)
+
+
 def adam(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     """One Adam step (Kingma & Ba 2015, Algorithm 1) -> (params, m, v)."""
     m = beta1 * m + (1.0 - beta1) * grad

@@ -121,3 +121,60 @@ def test_encoding_by_hand_and_label_invariance():
     X2, slot2 = mlp.encode(comp2, [3], pos2, prev2, 2000.0, 0.1)
     np.testing.assert_array_equal(X, X2)
     assert [perm[c] for c in slot2[0, :3]] == slot[0, :3].tolist()
+
+
+def test_accumulation_bound_holds_for_float32_sums_in_any_order():
+    """The per-element bound used by the layer checks: float32 sums of
+    bfloat16 products, taken in four different orders (sequential both
+    ways, pairwise, shuffled), stay within accumulation_bound of the exact
+    sum; the bound is a small multiple of the worst observed error."""
+    rng = np.random.default_rng(11)
+    worst_ratio = 0.0
+    for K in (32, 160, 256):
+        h = mlp.bf16(np.maximum(rng.normal(0, 1, size=(40, K)), 0))
+        W = rng.uniform(-0.2, 0.2, size=(24, K))
+        b = rng.uniform(-0.5, 0.5, size=24)
+        a, e = mlp.dense_with_bound(h, W, b)
+        Wb = mlp.bf16(W).astype(np.float32)
+        hf = h.astype(np.float32)
+        for r in range(h.shape[0]):
+            for n in range(W.shape[0]):
+                terms = list((hf[r] * Wb[n]).astype(np.float32)) + [np.float32(b[n])]
+                orders = [terms, terms[::-1], [terms[i] for i in rng.permutation(len(terms))]]
+                sums = []
+                for t in orders:
+                    acc = np.float32(0)
+                    for x in t:
+                        acc = np.float32(acc + x)
+                    sums.append(acc)
+                pair = np.asarray(terms, np.float32)
+                while pair.size > 1:
+                    if pair.size % 2:
+                        pair = np.append(pair, np.float32(0))
+                    pair = (pair[0::2] + pair[1::2]).astype(np.float32)
+                sums.append(pair[0])
+                for s in sums:
+                    err = abs(float(s) - a[r, n])
+                    assert err <= e[r, n], (K, r, n, err, e[r, n])
+                    worst_ratio = max(worst_ratio, err / e[r, n])
+    assert worst_ratio < 0.5
+
+
+def test_bf16_interval_brackets_rounding_and_catches_a_dropped_bias():
+    """Every float32 in [a - e, a + e] rounds (after ReLU) into the
+    interval; the interval is a single value away from rounding
+    boundaries; leaving out a bias moves the value outside it."""
+    rng = np.random.default_rng(12)
+    h = mlp.bf16(np.maximum(rng.normal(0, 1, size=(64, 256)), 0))
+    W = rng.uniform(-0.06, 0.06, size=(256, 256))
+    b = rng.uniform(-0.5, 0.5, size=256)
+    a, e = mlp.dense_with_bound(h, W, b)
+    lo, hi = mlp.bf16_interval(a, e, relu=True)
+    for frac in (-1.0, -0.5, 0.0, 0.5, 1.0):
+        v = mlp.bf16(np.maximum(a + frac * e, 0.0))
+        assert ((v >= lo) & (v <= hi)).all()
+    assert (lo == hi).mean() > 0.8
+    a_nobias, _ = mlp.dense_with_bound(h, W)
+    v = mlp.bf16(np.maximum(a_nobias, 0.0))
+    outside = (v < lo) | (v > hi)
+    assert outside.mean() > 0.5
