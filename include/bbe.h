@@ -426,6 +426,16 @@ int bbe_mlp_load(const char *path, int max_batch, bbe_mlp **out);
 int bbe_mlp_forward(const bbe_mlp *m, const uint16_t *x, const int32_t *n_valid, int batch,
                     float *probs, float *entropy, float *logits, void *stream);
 
+/* The forward pass of bbe_mlp_forward, also returning what each hidden
+ * layer feeds the next: hidden, device uint16 [3][batch][256], receives the
+ * bfloat16 bit patterns of h1, h2 and h3 (after bias and ReLU, rounded to
+ * nearest even), so that every layer can be checked on its own inputs;
+ * logits as in bbe_mlp_forward (may be NULL).
+ * Errors: BBE_EINVAL (NULL network, x, n_valid or hidden; batch < 1),
+ * BBE_EDEVICE.                                                              */
+int bbe_mlp_forward_hidden(const bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
+                           int batch, uint16_t *hidden, float *logits, void *stream);
+
 /* Mean soft cross-entropy of `batch` (1..max_batch) rows against target
  * (device float [batch][20], each row summing to 1 over its valid slots)
  * into loss (device float[1], overwritten), and its gradient into grad

@@ -73,6 +73,7 @@ SIGNATURES = {
     "bbe_mlp_save": (_I, [_P, ctypes.c_char_p]),
     "bbe_mlp_load": (_I, [ctypes.c_char_p, _I, _P]),
     "bbe_mlp_forward": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
+    "bbe_mlp_forward_hidden": (_I, [_P, _P, _P, _I, _P, _P, _P]),
     "bbe_mlp_loss_grad": (_I, [_P, _P, _P, _P, _I, _P, _P, _P]),
     "bbe_mlp_adam_step": (_I, [_P, _P, _F, _P]),
     "bbe_mlp_train_step": (_I, [_P, _P, _P, _P, _I, _F, _P, _P]),
@@ -390,6 +391,14 @@ class Mlp:
         _check(lib().bbe_mlp_forward(self._h, _dptr(x), _dptr(n_valid), int(x.shape[0]),
                                      _dptr(probs), _dptr(entropy), _dptr(logits),
                                      _stream(stream)))
+
+    def forward_hidden(self, x, n_valid, hidden, logits=None, stream=None):
+        """``bbe_mlp_forward_hidden``: hidden int16/uint16-bits CUDA tensor
+        [3, B, 256] receives h1, h2, h3."""
+        if tuple(hidden.shape) != (3, int(x.shape[0]), 256):
+            raise BBEError(EINVAL, "hidden must be [3, batch, 256]")
+        _check(lib().bbe_mlp_forward_hidden(self._h, _dptr(x), _dptr(n_valid), int(x.shape[0]),
+                                            _dptr(hidden), _dptr(logits), _stream(stream)))
 
     def loss_grad(self, x, n_valid, target, loss, grad=None, stream=None):
         _check(lib().bbe_mlp_loss_grad(self._h, _dptr(x), _dptr(n_valid), _dptr(target),

@@ -211,6 +211,21 @@ BBE_API int bbe_mlp_forward(const bbe_mlp* m, const uint16_t* x, const int32_t* 
     return ok();
 }
 
+BBE_API int bbe_mlp_forward_hidden(const bbe_mlp* m, const uint16_t* x, const int32_t* n_valid,
+                                   int batch, uint16_t* hidden, float* logits, void* stream) {
+    if (!m || !x || !n_valid || !hidden) return fail(BBE_EINVAL, "NULL argument");
+    if (batch < 1) return fail(BBE_EINVAL, "batch must be >= 1");
+    bbe::MlpFwdArgs a = fwd_args(m, x, n_valid, batch);
+    const size_t layer = (size_t)batch * bbe::kHid;
+    a.h1 = hidden;
+    a.h2 = hidden + layer;
+    a.h3 = hidden + 2 * layer;
+    a.logits = logits;
+    hipError_t e = bbe::launch_mlp_fwd(a, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "launching the forward pass");
+    return ok();
+}
+
 BBE_API int bbe_mlp_loss_grad(bbe_mlp* m, const uint16_t* x, const int32_t* n_valid,
                               const float* target, int batch, float* loss, float* grad,
                               void* stream) {

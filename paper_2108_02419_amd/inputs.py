@@ -170,6 +170,20 @@ def query_race(cfg: dict = CFG_QUERY) -> dict:
 SURROGATE_LAYERS = [(256, 160), (256, 256), (256, 256), (20, 256)]
 
 
+def surrogate_random(seed: int) -> np.ndarray:
+    """Surrogate parameters for checks: the weights of surrogate_init(seed)
+    with non-zero biases, uniform in +-0.5 for the hidden layers and +-1 for
+    the output layer."""
+    p = surrogate_init(seed)
+    rng = np.random.default_rng([seed, 0xB1A5])
+    o = 0
+    for i, (n, k) in enumerate(SURROGATE_LAYERS):
+        o += n * k
+        p[o:o + n] = rng.uniform(-1.0 if i == 3 else -0.5, 1.0 if i == 3 else 0.5, size=n)
+        o += n
+    return p
+
+
 def surrogate_init(seed: int = 4) -> np.ndarray:
     """Initial surrogate parameters (packed W1, b1, ..., W4, b4, float32):
     weights uniform in +-sqrt(6/fan_in) (He-uniform for ReLU layers; the

@@ -44,11 +44,16 @@ def _mc_answers(race, state, n, n_queries, requests, mc_sims, seed):
 
 
 def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
-        judge_sims=1_000_000, gate=None, max_rounds=None, log=print):
+        judge_sims=1_000_000, gate=None, max_rounds=None, log=print, on_round=None):
     """Steps the real race and answers every bettor each round.  A round's
     state goes to Monte-Carlo for every bettor when the surrogate's entropy
     exceeds `gate` (default 0.95 ln n); otherwise the surrogate answers and
-    a random `audit_frac` of the bettors is also answered by Monte-Carlo."""
+    a random `audit_frac` of the bettors is also answered by Monte-Carlo.
+    `on_round`, when given, receives each round's host copies: the state
+    (tick, pos, prev), the asked bettors and their request ids, the
+    Monte-Carlo answers (float64 [asked, 20], competitor order), the judge's
+    answer, the encoded features and slot map of every bettor, and the
+    surrogate's answers (float32 [bettors, 20], slot order)."""
     cfg = inputs.CFG_QUERY
     q = inputs.query_race(cfg)
     comp, seed, real_req = q["comp"], q["seed"], q["real_request"]
@@ -129,6 +134,12 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
         mc_c = mprobs.cpu().numpy()[:, :n]
         sur_err = float(np.abs(sur_c - judge).max())
         mc_err = float(np.abs(mc_c - judge[None, :]).max())
+        if on_round is not None:
+            on_round(dict(round=len(rounds), state=state, ask=ask, requests=base + ask,
+                          mc_seed=seed + 1, judge_request=0x40000000 | len(rounds),
+                          judge_seed=seed + 2, mc_probs=mprobs.cpu().numpy(), judge=judge,
+                          x=x.cpu().numpy(), slot=slot.cpu().numpy(),
+                          sur_probs=sprobs.cpu().numpy(), entropy=ent, flagged=flagged))
         rounds.append(dict(tick=tick, leader=float(pos.max()), entropy=float(ent[0]),
                            flagged=flagged, mc_queries=int(len(ask)), sur_err=sur_err,
                            mc_err=mc_err, answer_err=mc_err if flagged else sur_err,

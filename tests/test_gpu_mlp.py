@@ -32,54 +32,138 @@ def _bits(torch, X):
     return torch.tensor(u.astype(np.uint16).view(np.int16), device="cuda")
 
 
-def test_forward_matches_reference(torch):
+def _bf16_of_bits(h):
+    """bfloat16 bit patterns (int16 CUDA tensor) -> float64 numpy."""
+    u = h.cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return u.view(np.float32).astype(np.float64)
+
+
+def _check_layers(torch, net, params, X, n):
+    """Each layer of the GPU forward pass checked on its own GPU inputs:
+    h_k must be one of the bfloat16 values that rounding ReLU(h_{k-1} W_k^T +
+    b_k), evaluated with float32 accumulation in any order, can give
+    (oracle/mlp.py accumulation_bound: Higham's gamma_m for m products and
+    the bias); the logits must lie within that bound of h3 W4^T + b4.  A
+    dropped bias or a wrong operand moves most elements outside.  Returns
+    the GPU logits [B, 20] and the GPU probabilities."""
+    B = X.shape[0]
+    xt, nt = _bits(torch, X), torch.tensor(n, device="cuda")
+    hidden = torch.empty((3, B, 256), dtype=torch.int16, device="cuda")
+    logits = torch.empty((B, 32), dtype=torch.float32, device="cuda")
+    logits2 = torch.empty((B, 32), dtype=torch.float32, device="cuda")
+    probs = torch.empty((B, 20), dtype=torch.float32, device="cuda")
+    ent = torch.empty(B, dtype=torch.float32, device="cuda")
+    net.forward_hidden(xt, nt, hidden, logits)
+    net.forward(xt, nt, probs, ent, logits2)
+    torch.cuda.synchronize()
+    H = _bf16_of_bits(hidden)
+    P = ref.unpack(np.asarray(params, np.float32).astype(np.float64))
+    inp = ref.bf16(X)
+    for k in range(3):
+        a, e = ref.dense_with_bound(inp, P[f"W{k + 1}"], P[f"b{k + 1}"])
+        lo, hi = ref.bf16_interval(a, e, relu=True)
+        bad = (H[k] < lo) | (H[k] > hi)
+        assert not bad.any(), (k + 1, int(bad.sum()), np.argwhere(bad)[:4].tolist())
+        inp = H[k]
+    z, e = ref.dense_with_bound(inp, P["W4"], P["b4"])
+    zg = logits.cpu().numpy().astype(np.float64)[:, :20]
+    mask = np.arange(20)[None, :] < n[:, None]
+    assert (np.abs(zg - z) <= e)[mask].all(), np.abs(zg - z)[mask].max()
+    assert np.isneginf(zg[~mask]).all()
+    np.testing.assert_array_equal(logits2.cpu().numpy()[:, :20], logits.cpu().numpy()[:, :20])
+    # softmax and entropy of the GPU's own logits (float32 exp/log on the GPU)
+    zm = np.where(mask, zg, -np.inf)
+    ex = np.where(mask, np.exp(zm - zm.max(axis=1, keepdims=True)), 0.0)
+    q = ex / ex.sum(axis=1, keepdims=True)
+    np.testing.assert_allclose(probs.cpu().numpy(), q, rtol=0, atol=5e-6)
+    np.testing.assert_allclose(ent.cpu().numpy(), ref.entropy(q), rtol=0, atol=2e-5)
+    return zg, probs.cpu().numpy()
+
+
+def test_forward_layer_by_layer_with_biases(torch):
+    """Random non-zero biases, batches of one tile, ragged tails and several
+    tiles; also checked end to end against the reference from the features
+    alone (within 2e-3 on the probabilities)."""
     rng = np.random.default_rng(0)
-    params = inputs.surrogate_init(4)
+    params = inputs.surrogate_random(4)
     for B in [1, 63, 64, 200]:  # one tile, ragged tails, several tiles
-        announce(f"mlp forward B={B}")
+        announce(f"mlp forward per layer B={B}")
         X, n, _ = _features(rng, B)
         net = _bbe.Mlp(params, max_batch=256)
-        xt, nt = _bits(torch, X), torch.tensor(n, device="cuda")
-        probs = torch.empty((B, 20), dtype=torch.float32, device="cuda")
-        ent = torch.empty(B, dtype=torch.float32, device="cuda")
-        logits = torch.empty((B, 32), dtype=torch.float32, device="cuda")
-        net.forward(xt, nt, probs, ent, logits)
-        torch.cuda.synchronize()
-        z, q, _ = ref.forward(params.astype(np.float64), X, n)
-        zg = logits.cpu().numpy()[:, :20]
-        mask = np.arange(20)[None, :] < n[:, None]
-        scale = np.abs(z[mask]).max()
-        assert np.abs(zg[mask] - z[mask]).max() <= 2e-2 * scale + 1e-3
-        assert np.isneginf(zg[~mask]).all()
-        np.testing.assert_allclose(probs.cpu().numpy(), q, atol=2e-3)
-        np.testing.assert_allclose(ent.cpu().numpy(), ref.entropy(q), atol=5e-3)
+        _, pg = _check_layers(torch, net, params, X, n)
+        _, q, _ = ref.forward(params.astype(np.float64), X, n)
+        np.testing.assert_allclose(pg, q, atol=2e-3)
 
 
-def test_gradients_match_reference(torch):
-    rng = np.random.default_rng(1)
-    params = inputs.surrogate_init(4)
-    B = 300
-    X, n, T = _features(rng, B)
-    net = _bbe.Mlp(params, max_batch=512)
+def test_forward_layer_by_layer_after_adam_steps(torch):
+    """After training steps the kernels use the refreshed bfloat16 copies of
+    the updated master parameters, biases included."""
+    rng = np.random.default_rng(6)
+    params = inputs.surrogate_random(5)
+    X, n, T = _features(rng, 256)
+    net = _bbe.Mlp(params, max_batch=256)
+    xt, nt, tt = _bits(torch, X), torch.tensor(n, device="cuda"), torch.tensor(T, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    announce("mlp 5 Adam steps, then forward per layer")
+    for _ in range(5):
+        net.train_step(xt, nt, tt, 3e-3, loss)
+    torch.cuda.synchronize()
+    trained = net.params()
+    moved = ref.unpack(trained.astype(np.float64))
+    start = ref.unpack(params.astype(np.float64))
+    for name in moved:  # every tensor, biases too, was updated
+        assert not np.array_equal(moved[name], start[name]), name
+    Xe, ne, _ = _features(rng, 130)
+    _check_layers(torch, net, trained, Xe, ne)
+
+
+def _grad_check(torch, net, params, X, n, T):
+    B = X.shape[0]
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
     grad = torch.empty(_bbe.MLP_NPARAMS, dtype=torch.float32, device="cuda")
     net.loss_grad(_bits(torch, X), torch.tensor(n, device="cuda"),
                   torch.tensor(T, device="cuda"), loss, grad)
     torch.cuda.synchronize()
-    l_ref, g_ref = ref.loss_and_grad(params.astype(np.float64), X, n, T)
-    assert abs(loss.item() - l_ref) <= 1e-4 * abs(l_ref)
+    l_ref, g_ref = ref.loss_and_grad(np.asarray(params, np.float32).astype(np.float64), X, n, T)
+    assert abs(loss.item() - l_ref) <= 1e-4 * abs(l_ref), (B, loss.item(), l_ref)
     g = grad.cpu().numpy().astype(np.float64)
     G, R = ref.unpack(g), ref.unpack(g_ref)
     for name in G:
         err = np.linalg.norm(G[name] - R[name]) / max(np.linalg.norm(R[name]), 1e-30)
         assert err <= 1e-3, (name, err)
+    return grad.cpu().numpy()
+
+
+def test_gradients_match_reference(torch):
+    """Non-zero biases; the bias gradients are compared like the weights'."""
+    rng = np.random.default_rng(1)
+    params = inputs.surrogate_random(4)
+    X, n, T = _features(rng, 300)
+    net = _bbe.Mlp(params, max_batch=512)
+    announce("mlp gradients B=300 with biases")
+    _grad_check(torch, net, params, X, n, T)
+
+
+def test_gradients_match_reference_after_adam_steps(torch):
+    rng = np.random.default_rng(7)
+    params = inputs.surrogate_random(6)
+    X, n, T = _features(rng, 200)
+    net = _bbe.Mlp(params, max_batch=256)
+    xt, nt, tt = _bits(torch, X), torch.tensor(n, device="cuda"), torch.tensor(T, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    announce("mlp 4 Adam steps, then gradients")
+    for _ in range(4):
+        net.train_step(xt, nt, tt, 3e-3, loss)
+    torch.cuda.synchronize()
+    X2, n2, T2 = _features(rng, 200)
+    _grad_check(torch, net, net.params(), X2, n2, T2)
 
 
 def test_gradients_are_reproducible_over_several_row_chunks(torch):
     """1000 rows (four 256-row chunks of the weight-gradient kernel): the
     gradient matches the reference and two calls give the same bits."""
     rng = np.random.default_rng(5)
-    params = inputs.surrogate_init(4)
+    params = inputs.surrogate_random(4)
     B = 1000
     X, n, T = _features(rng, B)
     announce(f"mlp gradients B={B}, twice")
