@@ -295,6 +295,20 @@ int bbe_prefix_batch(const bbe_request *reqs, const uint32_t *sims, const float 
                      uint64_t seed, uint32_t *tick_out, float *pos_out, float *prev_out,
                      void *stream);
 
+/* bbe_prefix_batch for callers that cannot allocate memory (code that must
+ * not call hipMalloc, such as tight serving loops or harnesses that forbid
+ * it): same arguments, same outputs, same errors, but no device or host
+ * allocation.  The request descriptors are staged in a fixed device array
+ * of BBE_PREFIX_NOALLOC_MAX entries (about 3 MB), one per GPU, held until
+ * the process ends; n > BBE_PREFIX_NOALLOC_MAX is rejected with BBE_EINVAL.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (from several threads or streams) race and must not be made.  Returns
+ * after the work completed.                                                 */
+#define BBE_PREFIX_NOALLOC_MAX 4096
+int bbe_prefix_batch_noalloc(const bbe_request *reqs, const uint32_t *sims, const float *targets,
+                             int n, uint64_t seed, uint32_t *tick_out, float *pos_out,
+                             float *prev_out, void *stream);
+
 /* ------------------------------------------------------------------ */
 /* In play: the race the bettors watch and the cheap bettor rules.      */
 /* ------------------------------------------------------------------ */

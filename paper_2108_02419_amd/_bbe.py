@@ -67,6 +67,7 @@ SIGNATURES = {
     "bbe_batch_plan_info": (_I, [_P, _P, _P, _P, _P]),
     "bbe_batch_plan_free": (None, [_P]),
     "bbe_prefix_batch": (_I, [_P, _P, _P, _I, _U64, _P, _P, _P, _P]),
+    "bbe_prefix_batch_noalloc": (_I, [_P, _P, _P, _I, _U64, _P, _P, _P, _P]),
     "bbe_mlp_create": (_I, [_P, _I, _P]),
     "bbe_mlp_free": (None, [_P]),
     "bbe_mlp_get_params": (_I, [_P, _P]),
@@ -351,6 +352,24 @@ def prefix_batch(specs, sims, targets, seed, tick_out, pos_out, prev_out, stream
     _check(lib().bbe_prefix_batch(arr, sims.ctypes.data, targets.ctypes.data, n_reqs, seed,
                                   _dptr(tick_out), _dptr(pos_out), _dptr(prev_out),
                                   _stream(stream)))
+    del keep
+
+
+PREFIX_NOALLOC_MAX = 4096
+
+
+def prefix_batch_noalloc(specs, sims, targets, seed, tick_out, pos_out, prev_out, stream=None):
+    """``bbe_prefix_batch_noalloc``: as prefix_batch, with the request
+    descriptors in the library's fixed per-GPU workspace (at most
+    PREFIX_NOALLOC_MAX requests; calls must not overlap on one GPU)."""
+    arr, n_reqs, keep = _requests(specs)
+    sims = np.ascontiguousarray(sims, dtype=np.uint32)
+    targets = np.ascontiguousarray(targets, dtype=np.float32)
+    if sims.shape != (n_reqs,) or targets.shape != (n_reqs,):
+        raise BBEError(EINVAL, "sims and targets need one entry per request")
+    _check(lib().bbe_prefix_batch_noalloc(arr, sims.ctypes.data, targets.ctypes.data, n_reqs,
+                                          seed, _dptr(tick_out), _dptr(pos_out),
+                                          _dptr(prev_out), _stream(stream)))
     del keep
 
 

@@ -389,6 +389,23 @@ BBE_API int bbe_batch_plan_info(const bbe_batch_plan* plan, int* waves_per_block
 
 BBE_API void bbe_batch_plan_free(bbe_batch_plan* plan) { destroy(plan); }
 
+namespace {
+
+// One request of an in-play state batch: the descriptor bbe_prefix_batch and
+// bbe_prefix_batch_noalloc hand to the kernel.
+int fill_prefix_desc(const bbe_request& q, uint32_t sim, float target, int idx,
+                     bbe::ReqDesc& d) {
+    int rc = fill_desc(q, idx, d);
+    if (rc != BBE_OK) return rc;
+    if (!std::isfinite(target) || !(target < q.race->L))
+        return fail(BBE_EINVAL, "request %d: target must be finite and < track length", idx);
+    d.prefix_sim = sim;
+    d.target = target;
+    return BBE_OK;
+}
+
+}  // namespace
+
 BBE_API int bbe_prefix_batch(const bbe_request* reqs, const uint32_t* sims, const float* targets,
                              int n, uint64_t seed, uint32_t* tick_out, float* pos_out,
                              float* prev_out, void* stream) {
@@ -396,12 +413,8 @@ BBE_API int bbe_prefix_batch(const bbe_request* reqs, const uint32_t* sims, cons
     if (!tick_out || !pos_out || !prev_out) return fail(BBE_EINVAL, "NULL output");
     std::vector<bbe::ReqDesc> h(n);
     for (int i = 0; i < n; ++i) {
-        int rc = fill_desc(reqs[i], i, h[i]);
+        int rc = fill_prefix_desc(reqs[i], sims[i], targets[i], i, h[i]);
         if (rc != BBE_OK) return rc;
-        if (!std::isfinite(targets[i]) || !(targets[i] < reqs[i].race->L))
-            return fail(BBE_EINVAL, "request %d: target must be finite and < track length", i);
-        h[i].prefix_sim = sims[i];
-        h[i].target = targets[i];
     }
     bbe::ReqDesc* d = nullptr;
     if (hipMalloc(&d, sizeof(bbe::ReqDesc) * n) != hipSuccess)
@@ -413,6 +426,76 @@ BBE_API int bbe_prefix_batch(const bbe_request* reqs, const uint32_t* sims, cons
                                      pos_out, prev_out, s);
     hipError_t e2 = hipStreamSynchronize(s);
     (void)hipFree(d);
+    if (e != hipSuccess) return hip_fail(e, "in-play state batch");
+    if (e2 != hipSuccess) return hip_fail(e2, "in-play state batch");
+    return ok();
+}
+
+// ---------------------------------------------------------------------------
+// bbe_prefix_batch without allocations: the request descriptors go to a
+// fixed device array instead of a per-call hipMalloc.  The array exists once
+// per GPU for the life of the process; host code reaches it only through
+// the address hipGetSymbolAddress returns on that GPU (the array's own name
+// is a host-side stand-in there).
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) bbe::ReqDesc scratch[BBE_PREFIX_NOALLOC_MAX];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+bbe::ReqDesc* g_scratch_ptr[kMaxDevices] = {};
+
+// Address of the current GPU's copy of `scratch`, looked up once per GPU
+// with that GPU current.
+int scratch_on_current_device(bbe::ReqDesc** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(BBE_EDEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "looking up the static workspace");
+        g_scratch_ptr[dev] = static_cast<bbe::ReqDesc*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return BBE_OK;
+}
+
+}  // namespace
+
+BBE_API int bbe_prefix_batch_noalloc(const bbe_request* reqs, const uint32_t* sims,
+                                     const float* targets, int n, uint64_t seed,
+                                     uint32_t* tick_out, float* pos_out, float* prev_out,
+                                     void* stream) {
+    if (!reqs || !sims || !targets || n < 1) return fail(BBE_EINVAL, "bad batch arguments");
+    if (n > BBE_PREFIX_NOALLOC_MAX)
+        return fail(BBE_EINVAL, "n = %d exceeds the static workspace of %d requests", n,
+                    BBE_PREFIX_NOALLOC_MAX);
+    if (!tick_out || !pos_out || !prev_out) return fail(BBE_EINVAL, "NULL output");
+    bbe::ReqDesc* d = nullptr;
+    int rc = scratch_on_current_device(&d);
+    if (rc != BBE_OK) return rc;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    // descriptors staged through a fixed host block, one piece at a time
+    constexpr int kPiece = 32;
+    bbe::ReqDesc h[kPiece];
+    for (int i0 = 0; i0 < n; i0 += kPiece) {
+        const int m = std::min(kPiece, n - i0);
+        for (int j = 0; j < m; ++j) {
+            rc = fill_prefix_desc(reqs[i0 + j], sims[i0 + j], targets[i0 + j], i0 + j, h[j]);
+            if (rc != BBE_OK) return rc;  // nothing launched yet; earlier pieces are unused
+        }
+        hipError_t e = hipMemcpyAsync(d + i0, h, sizeof(bbe::ReqDesc) * m,
+                                      hipMemcpyHostToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);  // h is reused by the next piece
+        if (e != hipSuccess) return hip_fail(e, "staging the request descriptors");
+    }
+    hipError_t e = bbe::launch_prefix_batch(d, n, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                            tick_out, pos_out, prev_out, s);
+    hipError_t e2 = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "in-play state batch");
     if (e2 != hipSuccess) return hip_fail(e2, "in-play state batch");
     return ok();

@@ -241,3 +241,20 @@ def test_mlp_load_rejects_bad_files(L, tmp_path):
         assert L.bbe_last_error().decode()
     assert L.bbe_mlp_load(None, 8, ctypes.byref(out)) == _bbe.EINVAL
     assert L.bbe_mlp_save(None, b"/tmp/x") == _bbe.EINVAL
+
+
+def test_prefix_batch_noalloc_rejects_before_device_work(L):
+    """More requests than the fixed workspace holds, and NULL outputs, are
+    rejected with BBE_EINVAL before anything touches a device."""
+    race = _bbe.Race(np.array(GOOD, np.float32), 2000.0)
+    for n, outs in ((_bbe.PREFIX_NOALLOC_MAX + 1, (1, 1, 1)), (2, (None, 1, 1))):
+        arr, keep = _bbe._request_array([(race, None, 0, 1, i, 0) for i in range(n)])
+        sims = np.zeros(n, np.uint32)
+        targets = np.full(n, 100.0, np.float32)
+        ptrs = [None if o is None else ctypes.c_void_p(16) for o in outs]
+        rc = L.bbe_prefix_batch_noalloc(arr, sims.ctypes.data, targets.ctypes.data, n, 1,
+                                        *ptrs, None)
+        assert rc == _bbe.EINVAL
+        msg = L.bbe_last_error().decode()
+        assert ("static workspace" in msg) == (n > _bbe.PREFIX_NOALLOC_MAX), msg
+        del keep
