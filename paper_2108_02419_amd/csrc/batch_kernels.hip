@@ -30,16 +30,18 @@ __global__ void fill_u32_kernel(uint32_t* __restrict__ p, uint32_t v, int n) {
 __global__ void batch_probs_kernel(const unsigned long long* __restrict__ wins,
                                    const ReqDesc* __restrict__ reqs, int n_reqs,
                                    double* __restrict__ probs) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int r = i / kMaxN, c = i - r * kMaxN;
-    if (r >= n_reqs) return;
+    // 64-bit index: n_reqs * 20 may exceed 2^31
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t r = i / kMaxN;
+    const int c = (int)(i - r * kMaxN);
+    if (r >= (size_t)n_reqs) return;
     const int n = reqs[r].rc.n;
-    const unsigned long long* row = wins + (size_t)r * kMaxN;
+    const unsigned long long* row = wins + r * kMaxN;
     unsigned long long tot = 0;
     for (int k = 0; k < n; ++k) tot += row[k];
     double p = 0.0;
     if (c < n) p = tot ? (double)row[c] / (double)tot : 1.0 / (double)n;
-    probs[(size_t)r * kMaxN + c] = p;
+    probs[r * kMaxN + c] = p;
 }
 
 // In-play states for a batch: lane i advances simulation prefix_sim of

@@ -60,13 +60,15 @@ __global__ void zero_u64_kernel(unsigned long long* __restrict__ p, int n) {
 
 __global__ void win_probs_kernel(const unsigned long long* __restrict__ wins, int n_rows, int n,
                                  int stride, double* __restrict__ probs) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int r = i / n, c = i - r * n;
-    if (r >= n_rows) return;
-    const unsigned long long* row = wins + (size_t)r * stride;
+    // 64-bit index: n_rows * n may exceed 2^31
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t r = i / (size_t)n;
+    const int c = (int)(i - r * (size_t)n);
+    if (r >= (size_t)n_rows) return;
+    const unsigned long long* row = wins + r * (size_t)stride;
     unsigned long long tot = 0;
     for (int k = 0; k < n; ++k) tot += row[k];
-    probs[(size_t)r * stride + c] = tot ? (double)row[c] / (double)tot : 1.0 / (double)n;
+    probs[r * (size_t)stride + c] = tot ? (double)row[c] / (double)tot : 1.0 / (double)n;
 }
 
 // ---------------------------------------------------------------- launchers
