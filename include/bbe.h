@@ -232,18 +232,24 @@ typedef struct bbe_request {
 typedef struct bbe_batch_plan bbe_batch_plan;
 
 /* Plan flag: time candidate launch shapes (waves per workgroup, simulations
- * per work item) on the batch itself and keep the fastest; the choice is
- * cached per device and batch size class for later plans. */
+ * per work item, workgroups per CU) on the batch itself and keep the
+ * fastest; the choice is cached per device and batch size class for later
+ * plans, in memory and in a JSON file ($BBE_TUNE_CACHE if set, an empty
+ * value for none; else $XDG_CACHE_HOME/bbe/tune.json or
+ * $HOME/.cache/bbe/tune.json) keyed by the device (architecture, name, CU
+ * count) and the library's kernel sources, so that later processes skip
+ * the timing. */
 #define BBE_PLAN_AUTOTUNE 1u
 
 /* Builds a plan for n_reqs (>= 1) requests (the many dry-run requests of
  * in-play bettors, paper Section 3 and Section 6): copies the request
- * descriptors and a work list (requests split into work items of up to 64
- * simulations per generation, ordered by competitor count and expected
- * length, longest first) to the device, optionally autotunes, and captures
- * into a HIP graph the whole launch sequence: clear the outputs, reset the
- * work queues, run one persistent kernel per competitor count present
- * (each instantiated for its count), compute probabilities.
+ * descriptors and a work list (requests split into work items of whole
+ * generations of 64 simulations, ordered by expected competitor-steps,
+ * largest first) to the device, optionally autotunes, and captures into a
+ * HIP graph the whole launch sequence: clear the outputs, reset the work
+ * queue, run one persistent kernel over every item (each item with the
+ * kernel's instance for its competitor count; races with a time term of R
+ * in a second launch of the paced variant), compute probabilities.
  *   win_counts  device uint64[n_reqs][BBE_MAX_COMPETITORS]: row r receives
  *               request r's win counts (columns >= its n stay 0).
  *   probs       device double[n_reqs][BBE_MAX_COMPETITORS] or NULL: row r
@@ -480,7 +486,8 @@ int bbe_mlp_train_step(bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
  * rho/0.2 and (T - T_min)/10 with T = (L-d)/((lo+hi)*0.5*(1 + rho*d/L))
  * the expected remaining ticks and T_min the state's smallest (all 0 for
  * padding), where dt is the tick length in seconds the race parameters are
- * expressed in.  Outputs: x [batch][160]; slot_comp int32 [batch][20] or
+ * expressed in.  Outputs: x [batch][160] (16-byte aligned, else
+ * BBE_EINVAL); slot_comp int32 [batch][20] or
  * NULL, the competitor in each slot (-1 for padding).  With probs (device
  * double [batch][20], competitor order, e.g. from bbe_batch_plan_create)
  * the matching target (device float [batch][20]) receives them in slot

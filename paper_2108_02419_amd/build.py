@@ -31,10 +31,22 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
+def kernel_hash() -> str:
+    """Hash of the kernel sources (keys the persistent tuning cache)."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(CSRC, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()[:16]
+
+
 def compile_flags() -> list[str]:
     return [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",
             "-fno-fast-math", "-fvisibility=hidden", "-Wall",
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+            f'-DBBE_KERNEL_HASH="{kernel_hash()}"',
             "-I", INCLUDE, "-I", CSRC]
 
 

@@ -2,16 +2,15 @@
 // persistent launch (the paper's dry-run workload: many bettors each asking
 // for their own simulations of the race in play, Sections 3 and 6).
 //
-// batch_mc_kernel<N>: one persistent launch per competitor count present in
-// the batch (each with the register budget of its own N), grid sized to the
+// batch_mc_kernel: one persistent launch for the whole batch (a second one
+// for races with a time term of R, the paced variant), grid sized to the
 // resident capacity of the GPU; every wave repeatedly takes the next work
-// item of its group from a global atomic counter (one atomic per item,
-// issued by lane 0), runs that item's simulations one generation of 64 at a
-// time with the request's parameters in its LDS records, and flushes the
-// item's wins with one 64-bit atomic per competitor.  Within a group, items
-// are ordered by expected length, longest first, so the shortest work ends
-// the queue.  A group holding a race with a time term of R runs the paced
-// variant (which gives the same results on the group's other races).
+// item from a global atomic counter (one atomic per item, issued by lane
+// 0), runs that item's simulations one generation of 64 at a time with the
+// template instance of its competitor count and the request's parameters in
+// its LDS records, and flushes the item's wins with one 64-bit atomic per
+// competitor.  Items are ordered by expected work, largest first, so the
+// smallest work ends the queue.
 #include "batch_mc.hpp"
 #include "kernels.hpp"
 #include "race_sim.hpp"
@@ -118,55 +117,31 @@ __global__ void __launch_bounds__(64) prefix_batch_kernel(const ReqDesc* __restr
 
 // ---------------------------------------------------------------- launchers
 
-template <int N>
-static hipError_t launch_batch_n(const BatchArgs& a, int waves_per_block, int grid,
-                                 hipStream_t s) {
-    hipLaunchKernelGGL((batch_mc_kernel<N, false>), dim3(grid), dim3(64 * waves_per_block),
+hipError_t launch_batch_mc(const BatchArgs& a, int waves_per_block, int grid, bool paced,
+                           hipStream_t s) {
+    if (waves_per_block != 1 && waves_per_block != 2 && waves_per_block != 4)
+        return hipErrorInvalidValue;
+    if (paced) return launch_batch_mc_paced(a, waves_per_block, grid, s);
+    hipLaunchKernelGGL((batch_mc_kernel<false>), dim3(grid), dim3(64 * waves_per_block),
                        waves_per_block * kWaveBytes, s, a);
     return hipGetLastError();
 }
 
-template <int N>
-static int batch_occupancy_n(int waves_per_block) {
-    int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<N, false>,
-                                                     64 * waves_per_block,
-                                                     waves_per_block * kWaveBytes) != hipSuccess)
-        nb = 1;
-    return nb > 0 ? nb : 1;
-}
-
-template <int... I>
-static hipError_t dispatch_batch(int n, const BatchArgs& a, int w, int grid, hipStream_t s,
-                                 std::integer_sequence<int, I...>) {
-    using Fn = hipError_t (*)(const BatchArgs&, int, int, hipStream_t);
-    static constexpr Fn table[] = {launch_batch_n<I + 1>...};
-    return table[n - 1](a, w, grid, s);
-}
-
-template <int... I>
-static int dispatch_batch_occ(int n, int w, std::integer_sequence<int, I...>) {
-    using Fn = int (*)(int);
-    static constexpr Fn table[] = {batch_occupancy_n<I + 1>...};
-    return table[n - 1](w);
-}
-
-hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid, bool paced,
-                           hipStream_t s) {
-    if (n < 1 || n > kMaxN || (waves_per_block != 1 && waves_per_block != 2 &&
-                               waves_per_block != 4))
-        return hipErrorInvalidValue;
-    if (paced) return launch_batch_mc_paced(a, n, waves_per_block, grid, s);
-    return dispatch_batch(n, a, waves_per_block, grid, s,
-                          std::make_integer_sequence<int, kMaxN>{});
-}
-
-int batch_blocks_per_cu(int n, int waves_per_block, bool paced) {
-    if (n < 1 || n > kMaxN || waves_per_block < 1 || waves_per_block > 4) return 1;
-    if (paced) return batch_blocks_per_cu_paced(n, waves_per_block);
-    static int cache[kMaxN + 1][5] = {};
-    int& c = cache[n][waves_per_block];
-    if (!c) c = dispatch_batch_occ(n, waves_per_block, std::make_integer_sequence<int, kMaxN>{});
+int batch_blocks_per_cu(int waves_per_block, bool paced) {
+    if (waves_per_block < 1 || waves_per_block > 4) return 1;
+    if (paced) return batch_blocks_per_cu_paced(waves_per_block);
+    static int cache[5] = {};
+    int& c = cache[waves_per_block];
+    if (!c) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, batch_mc_kernel<false>,
+                                                         64 * waves_per_block,
+                                                         waves_per_block * kWaveBytes) !=
+                hipSuccess ||
+            nb < 1)
+            nb = 1;
+        c = nb;
+    }
     return c;
 }
 

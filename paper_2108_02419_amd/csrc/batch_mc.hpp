@@ -8,6 +8,8 @@
 #include "kernels.hpp"
 #include "race_sim.hpp"
 
+#include <utility>
+
 namespace bbe {
 
 // Per-wave LDS: draw table [kMaxN][64] floats, parameter records, win
@@ -78,17 +80,29 @@ __device__ __forceinline__ void run_chunk(const ReqDesc& rq, const Chunk& ch, ch
     }
 }
 
-// Waves per SIMD the register allocation aims for (4: the body fits in 128
-// VGPRs without spilling).
-template <int N, bool kPaced = false>
-constexpr int batch_waves_per_eu() {
-    return 4;
+// Runs a work item with the template instance of its competitor count (a
+// wave-uniform switch on n).
+template <bool kPaced, int... I>
+__device__ __forceinline__ void run_chunk_any(int n, const ReqDesc& rq, const Chunk& ch,
+                                              char* smem, uint32_t wbase, int lane, uint32_t k0,
+                                              uint32_t k1, unsigned long long* wins_row,
+                                              unsigned long long& steps,
+                                              std::integer_sequence<int, I...>) {
+    (void)((n == I + 1 ? (run_chunk<I + 1, kPaced>(rq, ch, smem, wbase, lane, k0, k1, wins_row,
+                                                    steps),
+                          true)
+                       : false) ||
+           ...);
 }
 
-// Persistent kernel for the work items of one competitor count; up to 4
-// waves per workgroup (blockDim.x = 64 * waves).
-template <int N, bool kPaced>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_waves_per_eu<N, kPaced>())))
+// The persistent kernel: one launch serves the work items of every
+// competitor count (one launch for the plain races, one for the paced);
+// waves take items from one global queue, ordered longest first across the
+// whole batch, so that the shortest items end the launch.  Up to 4 waves per
+// workgroup (blockDim.x = 64 * waves); the register budget aims at 4 waves
+// per SIMD (the largest instance fits in 128 VGPRs without spilling).
+template <bool kPaced>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4)))
     batch_mc_kernel(const BatchArgs a) {
     extern __shared__ __attribute__((aligned(16))) char smem[];  // waves * kWaveBytes
     const int wave = threadIdx.x >> 6;
@@ -101,8 +115,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(batch_
         ci = __builtin_amdgcn_readfirstlane(ci);
         if (ci >= a.n_chunks) break;
         const Chunk ch = a.chunks[ci];
-        run_chunk<N, kPaced>(a.reqs[ch.req], ch, smem, wbase, lane, a.k0, a.k1,
-                     a.wins + (size_t)ch.req * kMaxN, steps);
+        const int n = (int)__builtin_amdgcn_readfirstlane(ch.n);
+        run_chunk_any<kPaced>(n, a.reqs[ch.req], ch, smem, wbase, lane, a.k0, a.k1,
+                              a.wins + (size_t)ch.req * kMaxN, steps,
+                              std::make_integer_sequence<int, kMaxN>{});
     }
     steps = wave_sum_u64b(steps);
     if (a.steps && lane == 0 && steps) atomicAdd(a.steps, steps);

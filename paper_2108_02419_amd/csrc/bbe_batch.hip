@@ -3,7 +3,11 @@
 // a captured HIP graph of the whole launch sequence (include/bbe.h).
 #include "abi_internal.hpp"
 
+#include <sys/stat.h>
+#include <unistd.h>
+
 #include <algorithm>
+#include <cstdlib>
 #include <map>
 #include <mutex>
 #include <new>
@@ -16,17 +20,20 @@ namespace {
 struct Shape {
     int waves_per_block;
     int sims_per_item;  // multiple of 64: one work item = sims_per_item / 64 generations
+    int cu_share;       // workgroups per CU: the resident capacity divided by cu_share (1, 2)
 };
 
-// Autotune results per (device, size class of the work list).
+// Autotune results per (device, size class of the work list), in memory and
+// in a JSON file (see tune_cache_path) keyed by the device, the library's
+// kernel sources and the size class.
 std::mutex g_tune_mu;
 std::map<std::pair<int, int>, Shape> g_tuned;
+bool g_tune_file_read = false;
 
 struct Group {
-    int n;           // competitor count of every item in the group
     uint32_t first;  // its items: chunks[first .. first + count)
     uint32_t count;
-    bool paced;      // some item's race has a time term of R
+    bool paced;      // the items of races with a time term of R
 };
 
 struct Work {
@@ -56,32 +63,145 @@ double expected_ticks(const bbe::ReqDesc& r) {
 
 Work build_work(const std::vector<bbe::ReqDesc>& reqs, int sims_per_item) {
     Work w;
-    std::vector<std::pair<double, bbe::Chunk>> items;
+    // (paced, expected work) per item: plain items first, each launch's
+    // items largest first (competitor-steps: ticks x competitors x sims)
+    std::vector<std::pair<std::pair<bool, double>, bbe::Chunk>> items;
     for (size_t r = 0; r < reqs.size(); ++r) {
-        const double est = expected_ticks(reqs[r]);
-        for (uint32_t first = 0; first < reqs[r].n_sims; first += sims_per_item) {
+        const double ticks = expected_ticks(reqs[r]);
+        const bool paced = reqs[r].pace.paced != 0;
+        for (uint64_t first = 0; first < reqs[r].n_sims; first += (uint64_t)sims_per_item) {
             bbe::Chunk c;
             c.req = (uint32_t)r;
-            c.first = first;
-            c.count = std::min<uint32_t>(sims_per_item, reqs[r].n_sims - first);
+            c.first = (uint32_t)first;
+            c.count = (uint32_t)std::min<uint64_t>((uint64_t)sims_per_item,
+                                                   reqs[r].n_sims - first);
             c.n = (uint32_t)reqs[r].rc.n;
-            items.push_back({est, c});
+            items.push_back({{paced, ticks * c.n * c.count}, c});
         }
     }
     std::stable_sort(items.begin(), items.end(), [](const auto& a, const auto& b) {
-        if (a.second.n != b.second.n) return a.second.n > b.second.n;
-        return a.first > b.first;
+        if (a.first.first != b.first.first) return !a.first.first;
+        return a.first.second > b.first.second;
     });
     w.chunks.reserve(items.size());
     for (auto& it : items) {
-        const int n = (int)it.second.n;
-        if (w.groups.empty() || w.groups.back().n != n)
-            w.groups.push_back({n, (uint32_t)w.chunks.size(), 0u, false});
+        const bool paced = it.first.first;
+        if (w.groups.empty() || w.groups.back().paced != paced)
+            w.groups.push_back({(uint32_t)w.chunks.size(), 0u, paced});
         w.groups.back().count += 1;
-        if (reqs[it.second.req].pace.paced) w.groups.back().paced = true;
         w.chunks.push_back(it.second);
     }
     return w;
+}
+
+// ---------------------------------------------------------------------------
+// Persistent tuning cache.  A JSON file of entries {device, kernels,
+// size_class, waves_per_block, sims_per_item, cu_share}, one per line:
+// $BBE_TUNE_CACHE if set (empty: no file), else
+// $XDG_CACHE_HOME/bbe/tune.json or $HOME/.cache/bbe/tune.json.  An entry
+// applies to the device it was tuned on (architecture, name, CU count) and
+// to the kernel sources it was tuned with (a hash fixed at build time).
+// ---------------------------------------------------------------------------
+#ifndef BBE_KERNEL_HASH
+#define BBE_KERNEL_HASH "unknown"
+#endif
+
+std::string tune_cache_path() {
+    if (const char* p = std::getenv("BBE_TUNE_CACHE")) return p;
+    if (const char* x = std::getenv("XDG_CACHE_HOME"); x && *x)
+        return std::string(x) + "/bbe/tune.json";
+    if (const char* h = std::getenv("HOME"); h && *h) return std::string(h) + "/.cache/bbe/tune.json";
+    return "";
+}
+
+std::string device_key(int dev) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    char buf[400];
+    std::snprintf(buf, sizeof buf, "%s/%s/%d", prop.gcnArchName, prop.name,
+                  prop.multiProcessorCount);
+    for (char* c = buf; *c; ++c)
+        if (*c == '"' || *c == '\\' || (unsigned char)*c < 32) *c = '_';
+    return buf;
+}
+
+struct TuneEntry {
+    std::string device, kernels;
+    int size_class;
+    Shape shape;
+};
+
+std::vector<TuneEntry> read_tune_file(const std::string& path) {
+    std::vector<TuneEntry> out;
+    FILE* f = path.empty() ? nullptr : std::fopen(path.c_str(), "r");
+    if (!f) return out;
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        char dev[400], ker[80];
+        TuneEntry e;
+        if (std::sscanf(line,
+                        " {\"device\": \"%399[^\"]\", \"kernels\": \"%79[^\"]\", \"size_class\": %d, "
+                        "\"waves_per_block\": %d, \"sims_per_item\": %d, \"cu_share\": %d}",
+                        dev, ker, &e.size_class, &e.shape.waves_per_block,
+                        &e.shape.sims_per_item, &e.shape.cu_share) == 6) {
+            e.device = dev;
+            e.kernels = ker;
+            out.push_back(e);
+        }
+    }
+    std::fclose(f);
+    return out;
+}
+
+bool valid_shape(const Shape& s) {
+    return (s.waves_per_block == 1 || s.waves_per_block == 2 || s.waves_per_block == 4) &&
+           s.sims_per_item >= 64 && s.sims_per_item <= 65536 && s.sims_per_item % 64 == 0 &&
+           (s.cu_share == 1 || s.cu_share == 2);
+}
+
+// Loads this device's entries for these kernel sources (once per process).
+// Call with g_tune_mu held.
+void load_tune_cache(int dev) {
+    if (g_tune_file_read) return;
+    g_tune_file_read = true;
+    const std::string me = device_key(dev);
+    for (const TuneEntry& e : read_tune_file(tune_cache_path()))
+        if (e.device == me && e.kernels == BBE_KERNEL_HASH && valid_shape(e.shape))
+            g_tuned[{dev, e.size_class}] = e.shape;
+}
+
+// Adds or replaces one entry in the file (best effort: a file that cannot be
+// written leaves the in-memory result in place).  Call with g_tune_mu held.
+void store_tune_entry(int dev, int size_class, const Shape& sh) {
+    const std::string path = tune_cache_path();
+    if (path.empty()) return;
+    const std::string me = device_key(dev);
+    std::vector<TuneEntry> all = read_tune_file(path);
+    bool replaced = false;
+    for (TuneEntry& e : all)
+        if (e.device == me && e.kernels == BBE_KERNEL_HASH && e.size_class == size_class) {
+            e.shape = sh;
+            replaced = true;
+        }
+    if (!replaced) all.push_back({me, BBE_KERNEL_HASH, size_class, sh});
+    // create the directory one level up (the usual .../bbe/ folder)
+    const size_t slash = path.find_last_of('/');
+    if (slash != std::string::npos && slash > 0) (void)mkdir(path.substr(0, slash).c_str(), 0755);
+    const std::string tmp = path + ".tmp" + std::to_string((long)getpid());
+    FILE* f = std::fopen(tmp.c_str(), "w");
+    if (!f) return;
+    std::fprintf(f, "{\"entries\": [\n");
+    for (size_t i = 0; i < all.size(); ++i)
+        std::fprintf(f,
+                     "  {\"device\": \"%s\", \"kernels\": \"%s\", \"size_class\": %d, "
+                     "\"waves_per_block\": %d, \"sims_per_item\": %d, \"cu_share\": %d}%s\n",
+                     all[i].device.c_str(), all[i].kernels.c_str(), all[i].size_class,
+                     all[i].shape.waves_per_block, all[i].shape.sims_per_item,
+                     all[i].shape.cu_share, i + 1 < all.size() ? "," : "");
+    std::fprintf(f, "]}\n");
+    const bool good = std::fclose(f) == 0;
+    if (good) (void)std::rename(tmp.c_str(), path.c_str());
+    else (void)std::remove(tmp.c_str());
 }
 
 int size_class(size_t n_chunks) {
@@ -109,7 +229,8 @@ struct bbe_batch_plan {
     unsigned long long* wins = nullptr;
     double* probs = nullptr;
     unsigned long long* steps = nullptr;
-    Shape shape{4, 64};
+    Shape shape{4, 64, 1};
+    int item_sims = 64;  // simulations per work item in use (>= shape.sims_per_item)
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -135,8 +256,8 @@ hipError_t enqueue(bbe_batch_plan* p, hipStream_t s) {
         a.steps = p->steps;
         a.k0 = p->k0;
         a.k1 = p->k1;
-        if ((e = bbe::launch_batch_mc(a, gr.n, p->shape.waves_per_block, p->grids[g], gr.paced,
-                                      s)) != hipSuccess)
+        if ((e = bbe::launch_batch_mc(a, p->shape.waves_per_block, p->grids[g], gr.paced, s)) !=
+            hipSuccess)
             return e;
     }
     if (p->probs &&
@@ -145,8 +266,27 @@ hipError_t enqueue(bbe_batch_plan* p, hipStream_t s) {
     return hipSuccess;
 }
 
-int upload_work(bbe_batch_plan* p, const Shape& sh) {
-    Work w = build_work(p->host_reqs, sh.sims_per_item);
+// Work items of a batch: ceil(n_sims / 64) generations per request.
+uint64_t generation_count(const std::vector<bbe::ReqDesc>& reqs) {
+    uint64_t g = 0;
+    for (const bbe::ReqDesc& r : reqs) g += (r.n_sims + 63u) / 64u;
+    return g;
+}
+
+// Simulations per work item actually used for a shape: the shape's own,
+// raised (in whole generations) so that a batch has at most kMaxItems
+// items: a batch of very large requests gets fewer, longer items instead of
+// a work list of tens of millions.
+constexpr uint64_t kMaxItems = 1u << 20;
+int item_sims(const std::vector<bbe::ReqDesc>& reqs, int sims_per_item) {
+    const uint64_t gens = generation_count(reqs);
+    const uint64_t min_gens = (gens + kMaxItems - 1) / kMaxItems;
+    return (int)std::max<uint64_t>((uint64_t)sims_per_item, 64u * min_gens);
+}
+
+int upload_work(bbe_batch_plan* p, const Shape& sh, const std::vector<bbe::ReqDesc>& reqs) {
+    const int per_item = item_sims(reqs, sh.sims_per_item);
+    Work w = build_work(reqs, per_item);
     if (w.chunks.size() > p->chunk_cap) {
         if (p->d_chunks) (void)hipFree(p->d_chunks);
         p->d_chunks = nullptr;
@@ -160,12 +300,16 @@ int upload_work(bbe_batch_plan* p, const Shape& sh) {
     if (e != hipSuccess) return hip_fail(e, "copying the work list");
     p->n_chunks = (uint32_t)w.chunks.size();
     p->shape = sh;
+    p->item_sims = per_item;
     p->groups = w.groups;
     p->grids.clear();
     const int cus = device_cus();
     for (const Group& g : w.groups) {
-        // resident capacity, but no more waves than the group has items
-        long cap = (long)bbe::batch_blocks_per_cu(g.n, sh.waves_per_block, g.paced) * cus;
+        // resident capacity (or a share of it), but no more waves than the
+        // launch has items
+        long cap = std::max(1L, (long)bbe::batch_blocks_per_cu(sh.waves_per_block, g.paced) /
+                                    sh.cu_share) *
+                   cus;
         long need = ((long)g.count + sh.waves_per_block - 1) / sh.waves_per_block;
         p->grids.push_back((int)std::max(1L, std::min(cap, need)));
     }
@@ -257,12 +401,12 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
     hipStream_t s = static_cast<hipStream_t>(stream);
 
     // Launch shape: tuned on this batch, or from the cache, or the default.
-    Shape best{4, 64};
-    size_t base_items = build_work(p->host_reqs, 64).chunks.size();
-    std::pair<int, int> key{p->device, size_class(base_items)};
+    Shape best{4, 64, 1};
+    std::pair<int, int> key{p->device, size_class(generation_count(p->host_reqs))};
     bool have = false;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
+        load_tune_cache(p->device);
         auto it = g_tuned.find(key);
         if (it != g_tuned.end()) {
             best = it->second;
@@ -270,13 +414,24 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
         }
     }
     if ((flags & BBE_PLAN_AUTOTUNE) && !have) {
-        const Shape cands[] = {{4, 64}, {2, 64}, {1, 64}, {4, 128}, {2, 128}, {4, 256}};
+        const Shape cands[] = {{4, 64, 1},  {2, 64, 1},  {1, 64, 1}, {4, 128, 1},
+                               {2, 128, 1}, {1, 128, 1}, {4, 256, 1}, {4, 64, 2},
+                               {1, 64, 2}};
+        // Candidates are timed on the batch itself, or -- for a batch of
+        // more than kTuneGens generations -- on the same requests with their
+        // simulation counts scaled down to about that much work.
+        constexpr uint64_t kTuneGens = 1u << 16;
+        std::vector<bbe::ReqDesc> tune = p->host_reqs;
+        const uint64_t gens = generation_count(tune);
+        if (gens > kTuneGens)
+            for (bbe::ReqDesc& r : tune)
+                r.n_sims = (uint32_t)std::max<uint64_t>(1u, (uint64_t)r.n_sims * kTuneGens / gens);
         float best_ms = 1e30f;
         hipEvent_t ev0, ev1;
         (void)hipEventCreate(&ev0);
         (void)hipEventCreate(&ev1);
         for (const Shape& c : cands) {
-            int rc = upload_work(p, c);
+            int rc = upload_work(p, c, tune);
             if (rc != BBE_OK) {
                 (void)hipEventDestroy(ev0);
                 (void)hipEventDestroy(ev1);
@@ -303,8 +458,9 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
         (void)hipEventDestroy(ev1);
         std::lock_guard<std::mutex> lk(g_tune_mu);
         g_tuned[key] = best;
+        store_tune_entry(p->device, key.second, best);
     }
-    int rc = upload_work(p, best);
+    int rc = upload_work(p, best, p->host_reqs);
     if (rc != BBE_OK) {
         destroy(p);
         return rc;
@@ -382,7 +538,7 @@ BBE_API int bbe_batch_plan_info(const bbe_batch_plan* plan, int* waves_per_block
         for (int x : plan->grids) g = std::max(g, x);
         *grid = g;
     }
-    if (sims_per_item) *sims_per_item = plan->shape.sims_per_item;
+    if (sims_per_item) *sims_per_item = plan->item_sims;
     if (n_items) *n_items = (int)plan->n_chunks;
     return ok();
 }

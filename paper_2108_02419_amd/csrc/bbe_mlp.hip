@@ -300,6 +300,8 @@ BBE_API int bbe_encode_states(const float* comp, const int32_t* n, const float* 
     if ((probs == nullptr) != (target == nullptr))
         return fail(BBE_EINVAL, "probs and target go together");
     if (batch < 1) return fail(BBE_EINVAL, "batch must be >= 1");
+    if (reinterpret_cast<uintptr_t>(x) & 15u)
+        return fail(BBE_EINVAL, "x must be 16-byte aligned");
     if (!std::isfinite(track_len) || !(track_len > 0.0f) || !std::isfinite(dt) || !(dt > 0.0f))
         return fail(BBE_EINVAL, "track_len and dt must be finite and > 0");
     bbe::EncodeArgs a;

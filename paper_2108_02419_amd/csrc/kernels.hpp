@@ -95,26 +95,26 @@ struct Chunk {
     uint32_t n;
 };
 
-// One launch serves the work items of one competitor count: chunks[0 ..
-// n_chunks) all have chunk.n == N of the kernel.
+// One launch serves the work items chunks[0 .. n_chunks) of every
+// competitor count (chunk.n selects the template instance).
 struct BatchArgs {
     const ReqDesc* reqs;
     const Chunk* chunks;
     uint32_t n_chunks;
-    uint32_t* queue;            // this group's work-queue head, zeroed before launch
+    uint32_t* queue;            // the launch's work-queue head, zeroed before launch
     unsigned long long* wins;   // [n_reqs][kMaxN], zeroed before launch
     unsigned long long* steps;  // [1] or null, zeroed before launch
     uint32_t k0, k1;
 };
 
-// paced: the group holds a race with a time term of R (some gamma != 0)
-hipError_t launch_batch_mc(const BatchArgs& a, int n, int waves_per_block, int grid, bool paced,
+// paced: the items include a race with a time term of R (some gamma != 0)
+hipError_t launch_batch_mc(const BatchArgs& a, int waves_per_block, int grid, bool paced,
                            hipStream_t s);
-int batch_blocks_per_cu(int n, int waves_per_block, bool paced);
-// the paced variants (batch_kernels_paced.hip), used by the two above
-hipError_t launch_batch_mc_paced(const BatchArgs& a, int n, int waves_per_block, int grid,
+int batch_blocks_per_cu(int waves_per_block, bool paced);
+// the paced variant (batch_kernels_paced.hip), used by the two above
+hipError_t launch_batch_mc_paced(const BatchArgs& a, int waves_per_block, int grid,
                                  hipStream_t s);
-int batch_blocks_per_cu_paced(int n, int waves_per_block);
+int batch_blocks_per_cu_paced(int waves_per_block);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
 hipError_t launch_batch_probs(const unsigned long long* wins, const ReqDesc* reqs, int n_reqs,
                               double* probs, hipStream_t s);

@@ -361,58 +361,76 @@ __global__ void mlp_adam_kernel(const MlpAdamArgs a) {
     }
 }
 
-// State encoding: one thread per state.  Slots hold competitors by
-// position, leader first (equal positions: lower index first).  Positions
-// enter only relative to other competitors or to the line (bfloat16 keeps
-// about 2.5 significant digits: an absolute position would lose the gaps
-// that decide a race).  8 float32 features per slot, rounded to bfloat16:
-// remaining distance (L-d)/L, gap to the leader / (75 dt), gap to the slot
-// above / (7.5 dt) capped at 4 (4 for the leader), previous step / (7.5 dt),
-// mean free step (lo+hi)/(15 dt), (hi-lo)/(hi+lo), rho/0.2, and
-// (T - T_min)/10 with T = (L-d) / ((lo+hi)*0.5 * (1 + rho*d/L)) the expected
-// remaining ticks (R_c taken at the midpoint of the remaining distance);
-// zero padding.
-__global__ void encode_kernel(const EncodeArgs a) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.B) return;
-    const int n = min(max(a.n[b], 0), kMaxN);
-    const float* pos = a.pos + (size_t)b * kMaxN;
-    const float* prev = a.prev + (size_t)b * kMaxN;
-    const float* comp = a.comp + (size_t)b * kMaxN * 5;
-    uint16_t* x = a.x + (size_t)b * kIn;
-    for (int j = 0; j < kIn; ++j) x[j] = 0;
-    if (a.slot) for (int r = 0; r < kMaxN; ++r) a.slot[(size_t)b * kMaxN + r] = -1;
-    if (a.target) for (int r = 0; r < kMaxN; ++r) a.target[(size_t)b * kMaxN + r] = 0.0f;
-    if (n == 0) return;
+// State encoding: one state per half-wave (32 lanes), lane c of the half
+// for competitor c.  Slots hold competitors by position, leader first
+// (equal positions: lower index first): a competitor's slot is the number
+// of competitors ahead of it in that order.  Positions enter only relative
+// to other competitors or to the line (bfloat16 keeps about 2.5
+// significant digits: an absolute position would lose the gaps that decide
+// a race).  8 float32 features per slot, rounded to bfloat16: remaining
+// distance (L-d)/L, gap to the leader / (75 dt), gap to the slot above /
+// (7.5 dt) capped at 4 (4 for the leader), previous step / (7.5 dt), mean
+// free step (lo+hi)/(15 dt), (hi-lo)/(hi+lo), rho/0.2, and (T - T_min)/10
+// with T = (L-d) / ((lo+hi)*0.5 * (1 + rho*d/L)) the expected remaining
+// ticks (R_c taken at the midpoint of the remaining distance); zero
+// padding.  Each lane writes its slot's 8 features as one 16-byte store,
+// so a state's 320-byte row is written by 20 adjacent stores.
+__global__ void __launch_bounds__(256) encode_kernel(const EncodeArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int half = lane & 32;                // first lane of this state's half-wave
+    const int c = lane & 31;                   // competitor of this lane
+    const long b = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 5;  // state
+    const bool in = b < a.B;
+    const int n = in ? min(max(a.n[b], 0), kMaxN) : 0;
+    const bool act = c < n;
     const float L = a.track_len;
-    int inv[kMaxN];  // slot -> competitor
-    float T[kMaxN];
-    float tmin = __builtin_inff();
-    for (int c = 0; c < n; ++c) {
-        const float d = pos[c];
-        int r = 0;
-        for (int i = 0; i < n; ++i) {
-            const float di = pos[i];
-            r += (di > d || (di == d && i < c)) ? 1 : 0;
-        }
-        inv[r] = c;
-        const float lo = comp[c * 5 + 0], hi = comp[c * 5 + 1], rho = comp[c * 5 + 3];
-        const float rmid = 1.0f + rho * (d / L);
-        T[c] = (L - d) / (((lo + hi) * 0.5f) * rmid);
-        tmin = fminf(tmin, T[c]);
+    float d = 0.0f, s = 0.0f, lo = 0.0f, hi = 0.0f, rho = 0.0f;
+    if (act) {
+        d = a.pos[b * kMaxN + c];
+        s = a.prev[b * kMaxN + c];
+        const float* cp = a.comp + (b * kMaxN + c) * 5;
+        lo = cp[0];
+        hi = cp[1];
+        rho = cp[3];
     }
-    const float d_lead = pos[inv[0]];
-    for (int r = 0; r < n; ++r) {
-        const int c = inv[r];
-        const float d = pos[c];
-        const float lo = comp[c * 5 + 0], hi = comp[c * 5 + 1], rho = comp[c * 5 + 3];
-        const float gap = r == 0 ? 4.0f : fminf((pos[inv[r - 1]] - d) / a.c75, 4.0f);
-        const float f[8] = {(L - d) / L,         (d_lead - d) / a.c750, gap,
-                            prev[c] / a.c75,     (lo + hi) / a.c15,     (hi - lo) / (hi + lo),
-                            rho / 0.2f,          (T[c] - tmin) / 10.0f};
-        for (int j = 0; j < 8; ++j) x[r * 8 + j] = to_bf16(f[j]);
-        if (a.slot) a.slot[(size_t)b * kMaxN + r] = c;
-        if (a.target) a.target[(size_t)b * kMaxN + r] = (float)a.probs_in[(size_t)b * kMaxN + c];
+    const float rmid = 1.0f + rho * (d / L);
+    const float T = act ? (L - d) / (((lo + hi) * 0.5f) * rmid) : __builtin_inff();
+    // slot = competitors ahead; the slot above's position; the leader's
+    // position; the smallest expected remaining time
+    int slot = 0;
+    float d_above = __builtin_inff(), d_lead = -__builtin_inff(), tmin = __builtin_inff();
+    // every lane runs all kMaxN steps (the two halves may hold different n)
+    for (int i = 0; i < kMaxN; ++i) {
+        const float di = __shfl(d, half + i, 64);
+        const float Ti = __shfl(T, half + i, 64);
+        const bool valid = i < n;
+        const bool ahead = valid && (di > d || (di == d && i < c));
+        slot += ahead ? 1 : 0;
+        // the slot above is the lowest of those ahead in (position, index) order
+        d_above = ahead ? fminf(d_above, di) : d_above;
+        d_lead = valid ? fmaxf(d_lead, di) : d_lead;
+        tmin = valid ? fminf(tmin, Ti) : tmin;
+    }
+    if (!in || c >= kMaxN) return;
+    uint16_t* x = a.x + b * kIn;
+    if (act) {
+        const float gap = slot == 0 ? 4.0f : fminf((d_above - d) / a.c75, 4.0f);
+        const float f[8] = {(L - d) / L,     (d_lead - d) / a.c750, gap,
+                            s / a.c75,       (lo + hi) / a.c15,     (hi - lo) / (hi + lo),
+                            rho / 0.2f,      (T - tmin) / 10.0f};
+        uint4 v;
+        v.x = (uint32_t)to_bf16(f[0]) | ((uint32_t)to_bf16(f[1]) << 16);
+        v.y = (uint32_t)to_bf16(f[2]) | ((uint32_t)to_bf16(f[3]) << 16);
+        v.z = (uint32_t)to_bf16(f[4]) | ((uint32_t)to_bf16(f[5]) << 16);
+        v.w = (uint32_t)to_bf16(f[6]) | ((uint32_t)to_bf16(f[7]) << 16);
+        *reinterpret_cast<uint4*>(x + slot * 8) = v;
+        if (a.slot) a.slot[b * kMaxN + slot] = c;
+        if (a.target) a.target[b * kMaxN + slot] = (float)a.probs_in[b * kMaxN + c];
+    } else {
+        // lanes n .. 19 clear the padding slots n .. 19
+        *reinterpret_cast<uint4*>(x + c * 8) = make_uint4(0u, 0u, 0u, 0u);
+        if (a.slot) a.slot[b * kMaxN + c] = -1;
+        if (a.target) a.target[b * kMaxN + c] = 0.0f;
     }
 }
 
@@ -450,7 +468,8 @@ hipError_t launch_mlp_adam(const MlpAdamArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 hipError_t launch_encode(const EncodeArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(encode_kernel, dim3((a.B + 63) / 64), dim3(64), 0, s, a);
+    // 8 states per 256-thread workgroup
+    hipLaunchKernelGGL(encode_kernel, dim3((unsigned)(((long)a.B + 7) / 8)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 hipError_t launch_fill_f32(float* p, float v, int n, hipStream_t s) {

@@ -23,8 +23,25 @@ struct BlockLds {
     static constexpr uint32_t kSteps = kWins + 128;                        // u64
     static constexpr uint32_t kInit = kSteps + 16;  // start state: d0, s0 (f32[N]), id0 (u8[N])
     static constexpr uint32_t kIds = kInit + kMaxN * 12;  // [wave] finisher ids, u8[N][64]
-    static constexpr uint32_t kBytes = kIds + kWaves * N * 64;
+    // [wave] finish orders of the wave's current generation, u8[64][N]
+    static constexpr uint32_t kOrd = kIds + kWaves * N * 64;
+    static constexpr uint32_t kBytes = kOrd + kWaves * 64 * N;
 };
+
+// Copies `bytes` bytes of a wave's LDS order table to global memory with
+// coalesced 4-byte stores (byte stores for an unaligned destination and
+// for the tail).
+__device__ __forceinline__ void flush_orders(const char* tab, uint8_t* __restrict__ dst,
+                                             uint32_t bytes, int lane) {
+    uint32_t done = 0;
+    if ((reinterpret_cast<uintptr_t>(dst) & 3u) == 0) {
+        const uint32_t words = bytes >> 2;
+        for (uint32_t w = lane; w < words; w += 64)
+            reinterpret_cast<uint32_t*>(dst)[w] = reinterpret_cast<const uint32_t*>(tab)[w];
+        done = words << 2;
+    }
+    for (uint32_t i = done + lane; i < bytes; i += 64) dst[i] = (uint8_t)tab[i];
+}
 
 __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v) {
 #pragma unroll
@@ -86,17 +103,33 @@ __global__ void __launch_bounds__(kBlock)
     const uint64_t wave_stride = (uint64_t)gridDim.x * kWaves * 64;
     unsigned long long steps = 0ull;
 
+    // finish orders go to the wave's LDS table during a generation and to
+    // HBM in one coalesced flush at its end
+    char* otab = smem + Lay::kOrd + wave * (64 * N);
     for (uint64_t base = ((uint64_t)blockIdx.x * kWaves + wave) * 64; base < a.n_sims;
          base += wave_stride) {
         const uint64_t j = base + lane;
         const bool live = j < a.n_sims;
-        uint8_t* row = (a.orders && live) ? a.orders + j * N : nullptr;
+        uint8_t* row = (a.orders && live) ? reinterpret_cast<uint8_t*>(otab + lane * N) : nullptr;
         // re-read the start state from LDS each generation rather than
         // keeping it live (in registers) across the loop
         __asm__ volatile("" ::: "memory");
         run_generation<N, kPaced ? kPaceTable : kPaceOff, true, mc_skip_step<N>()>(
             smem, ucol, icol, pbase, L, s_d0, s_s0, s_id0, a.t0, live, a.sim_begin + (uint32_t)j,
             a.request, a.k0, a.k1, a.stop_after, row, s_wins, steps);
+        if (a.orders) {
+            // the wave's LDS operations complete in order; keep the compiler
+            // from moving the table's reads above the lanes' writes (and the
+            // next generation's writes above these reads)
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            const uint64_t rows = a.n_sims - base < 64 ? a.n_sims - base : 64;
+            flush_orders(otab, a.orders + base * N, (uint32_t)(rows * N), lane);
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        }
     }
 
     steps = wave_sum_u64(steps);

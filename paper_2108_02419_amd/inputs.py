@@ -161,6 +161,37 @@ def surrogate_states(n_states: int, cfg: dict = CFG_SURROGATE, first: int = 0) -
     return out
 
 
+SURROGATE_BLOCK = 65536  # states per block of surrogate_state_block
+
+
+def surrogate_state_block(block: int, count: int = SURROGATE_BLOCK,
+                          cfg: dict = CFG_SURROGATE) -> dict:
+    """Block `block` of the surrogate's states, drawn as arrays (the same
+    recipe as surrogate_states, one generator per block, so that 10^7
+    states take seconds): comp float32 [count, 20, 5] (zero rows past n),
+    n int32 [count], target float32 [count] (leader position at which the
+    state is taken), prefix_request uint32 [count] (request id of the run
+    that produces the state: PREFIX_REQUEST_BIT | global state index)."""
+    rng = np.random.default_rng([cfg["seed"], 0xB10C, block])
+    n = np.where(rng.uniform(size=count) < cfg["p_n20"], 20,
+                 rng.integers(cfg["n_lo"], cfg["n_hi"] + 1, size=count)).astype(np.int32)
+    mu = rng.uniform(6.0, 7.5, size=(count, MAX_N))
+    sigma = rng.uniform(1.0 / 3.0, 12.0 / 13.0, size=(count, MAX_N))
+    rho = rng.uniform(-0.2, 0.2, size=(count, MAX_N))
+    rem = rng.uniform(cfg["frac_lo"], cfg["frac_hi"], size=count)
+    dt = cfg["dt"]
+    comp = np.zeros((count, MAX_N, 5), dtype=np.float32)
+    comp[:, :, 0] = dt * mu * (1.0 - sigma)
+    comp[:, :, 1] = dt * mu * (1.0 + sigma)
+    comp[:, :, 2] = 1.0
+    comp[:, :, 3] = rho
+    comp[:, :, 4] = 2.0
+    comp[np.arange(MAX_N)[None, :] >= n[:, None]] = 0.0
+    index = block * SURROGATE_BLOCK + np.arange(count, dtype=np.int64)
+    return dict(comp=comp, n=n, target=(TRACK_LEN * (1.0 - rem)).astype(np.float32),
+                prefix_request=(PREFIX_REQUEST_BIT | (index & 0x7FFFFFFF)).astype(np.uint32))
+
+
 def query_race(cfg: dict = CFG_QUERY) -> dict:
     rng = np.random.default_rng(cfg["seed"])
     comp = competitor_params(rng, cfg["n"], cfg["dt"])

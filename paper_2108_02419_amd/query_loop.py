@@ -4,14 +4,16 @@ win probabilities at a fixed period (paper Section 3: RP(d) bettors; Section
 plus the bettors' dry-runs).
 
 Per round: the real race advances `every` ticks (its own random stream);
-all bettors query the surrogate on the new state; when the surrogate's
-entropy exceeds a gate every bettor's query goes to Monte-Carlo instead
-(each bettor its own simulations, as its own request), otherwise a random
-audit sample is also answered by Monte-Carlo; a high-sample Monte-Carlo
-judge measures the error of both.  Orchestration only -- every computation
-runs in the library's kernels.
+every bettor asks the surrogate on the new state; a 1% audit sample is also
+answered by Monte-Carlo (each bettor its own simulations, as its own
+request).  The surrogate serves the round unless its entropy is above a gate
+or it disagrees with the audit's pooled estimate; otherwise every bettor is
+answered by Monte-Carlo at a fallback size.  A high-sample Monte-Carlo judge
+measures the error of every answer, and the plain Monte-Carlo path (every
+bettor at the audit's size) is timed on a sample of rounds as the baseline.
+Orchestration only -- every computation runs in the library's kernels.
 
-    python -m paper_2108_02419_amd.query_loop --params bbe_out/surrogate/params.npy
+    python -m paper_2108_02419_amd.query_loop --params surrogate.bbemlp
 """
 from __future__ import annotations
 
@@ -31,7 +33,7 @@ L = inputs.TRACK_LEN
 
 def _mc_answers(race, state, n, n_queries, requests, mc_sims, seed):
     """Monte-Carlo answers for `n_queries` bettors on one state (each bettor
-    its own request); returns (plan, probs [n_queries, 20])."""
+    its own request); returns (plan, probs [n_queries, 20], wins)."""
     tick, pos, prev = state
     tab = _bbe.RequestTable([race] * n_queries, mc_sims, requests, 1,
                             tick=np.full(n_queries, tick, np.uint32),
@@ -40,26 +42,44 @@ def _mc_answers(race, state, n, n_queries, requests, mc_sims, seed):
     wins = torch.zeros((n_queries, 20), dtype=torch.int64, device="cuda")
     probs = torch.zeros((n_queries, 20), dtype=torch.float64, device="cuda")
     plan = _bbe.BatchPlan(tab, seed, wins, probs, None, autotune=True)
-    return plan, probs
+    return plan, probs, wins
+
+
+def _probs_from_wins(wins, n):
+    w = wins[:n].astype(np.float64)
+    tot = w.sum()
+    return w / tot if tot > 0 else np.full(n, 1.0 / n)
 
 
 def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
-        judge_sims=1_000_000, gate=None, max_rounds=None, log=print, on_round=None):
-    """Steps the real race and answers every bettor each round.  A round's
-    state goes to Monte-Carlo for every bettor when the surrogate's entropy
-    exceeds `gate` (default 0.95 ln n); otherwise the surrogate answers and
-    a random `audit_frac` of the bettors is also answered by Monte-Carlo.
+        fallback_sims=25_000, judge_sims=1_000_000, gate=None, audit_tol=0.0175,
+        baseline_every=10, max_rounds=None, log=print, on_round=None):
+    """Steps the real race and answers every bettor each round.
+
+    Each round: every bettor asks the surrogate (encode + forward, no
+    deduplication of equal states); a random `audit_frac` of the bettors
+    (at least one) is also answered by Monte-Carlo at `mc_sims` simulations
+    each, as their own requests.  The round is served by the surrogate
+    unless its entropy exceeds `gate` (default 0.95 ln n) or it differs from
+    the audit's pooled estimate (all audited simulations together) by more
+    than `audit_tol` for some competitor; otherwise every bettor is answered
+    by Monte-Carlo at `fallback_sims` simulations.  A Monte-Carlo judge at
+    `judge_sims` measures the error of every answer.  Every
+    `baseline_every`-th round also times the plain Monte-Carlo path (every
+    bettor at `mc_sims`): the rate the system is compared with.
+
     `on_round`, when given, receives each round's host copies: the state
-    (tick, pos, prev), the asked bettors and their request ids, the
-    Monte-Carlo answers (float64 [asked, 20], competitor order), the judge's
-    answer, the encoded features and slot map of every bettor, and the
-    surrogate's answers (float32 [bettors, 20], slot order)."""
+    (tick, pos, prev), the audited bettors and their request ids, their
+    Monte-Carlo answers (float64 [asked, 20], competitor order), the
+    judge's answer, the encoded features and slot map of every bettor, the
+    surrogate's answers (float32 [bettors, 20], slot order) and, in fallback
+    rounds, the fallback's answers."""
     cfg = inputs.CFG_QUERY
     q = inputs.query_race(cfg)
     comp, seed, real_req = q["comp"], q["seed"], q["real_request"]
     n = comp.shape[0]
     race = _bbe.Race(comp, L)
-    net = _bbe.Mlp(params, max_batch=8)
+    net = params if isinstance(params, _bbe.Mlp) else _bbe.Mlp(params, max_batch=8)
     dev = torch.device("cuda")
     rng = np.random.default_rng(seed)
     thr = 0.95 * math.log(n) if gate is None else float(gate)
@@ -75,11 +95,19 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
     pos_t = torch.empty(n, dtype=torch.float32, device=dev)
     prev_t = torch.empty(n, dtype=torch.float32, device=dev)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n_audit = max(1, int(round(audit_frac * n_bettors)))
+
+    def timed(fn):
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3
 
     state = None
     rounds = []
-    sur_s = mc_s = 0.0
-    sur_q = mc_q = 0
+    sur_s = audit_s = fb_s = base_s = 0.0
+    base_q = 0
     while max_rounds is None or len(rounds) < max_rounds:
         _bbe.race_advance(race, seed, real_req, 0, every, tick_t, pos_t, prev_t, state=state)
         torch.cuda.synchronize()
@@ -88,112 +116,140 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
             break  # the real race reached its first finisher
         pos, prev = pos_t.cpu().numpy().copy(), prev_t.cpu().numpy().copy()
         state = (tick, pos, prev)
+        k = len(rounds)
 
-        # every bettor asks the surrogate (no deduplication of equal states)
+        # every bettor asks the surrogate
         pos_b = torch.zeros((n_bettors, 20), dtype=torch.float32, device=dev)
         prev_b = torch.zeros((n_bettors, 20), dtype=torch.float32, device=dev)
         pos_b[:, :n] = pos_t
         prev_b[:, :n] = prev_t
         torch.cuda.synchronize()
-        e0.record()
-        _bbe.encode_states(comp_b, n_b, pos_b, prev_b, L, cfg["dt"], x, slot)
-        net.forward(x, n_b, sprobs, sent)
-        e1.record()
-        torch.cuda.synchronize()
-        t_sur = e0.elapsed_time(e1) / 1e3
+
+        def sur():
+            _bbe.encode_states(comp_b, n_b, pos_b, prev_b, L, cfg["dt"], x, slot)
+            net.forward(x, n_b, sprobs, sent)
+        t_sur = timed(sur)
         sur_s += t_sur
-        sur_q += n_bettors
-
+        sl = slot.cpu().numpy()[0]
+        sp = sprobs.cpu().numpy()[0]
+        sur_c = np.zeros(n)
+        for r in range(n):  # slot order -> competitor order
+            sur_c[sl[r]] = sp[r]
         ent = sent.cpu().numpy()
-        flagged = bool(ent[0] > thr)
-        ask = np.arange(n_bettors) if flagged else np.sort(
-            rng.choice(n_bettors, max(1, int(round(audit_frac * n_bettors))), replace=False))
-        base = (len(rounds) * n_bettors) & 0x3FFFFFFF
-        plan, mprobs = _mc_answers(race, state, n, len(ask), base + ask, mc_sims, seed + 1)
-        e0.record()
-        plan.launch()
-        e1.record()
-        torch.cuda.synchronize()
-        t_mc = e0.elapsed_time(e1) / 1e3
-        mc_s += t_mc
-        mc_q += len(ask)
-        plan.free()
 
-        jplan, jprobs = _mc_answers(race, state, n, 1, [0x40000000 | len(rounds)], judge_sims,
-                                    seed + 2)
+        # the audit: a random 1% of the bettors, Monte-Carlo each
+        ask = np.sort(rng.choice(n_bettors, n_audit, replace=False))
+        base = (k * n_bettors) & 0x3FFFFFFF
+        plan, mprobs, mwins = _mc_answers(race, state, n, len(ask), base + ask, mc_sims, seed + 1)
+        t_audit = timed(plan.launch)
+        audit_s += t_audit
+        plan.free()
+        pooled = _probs_from_wins(mwins.sum(dim=0).cpu().numpy(), n)
+        audit_gap = float(np.abs(sur_c - pooled).max())
+        flagged = bool(ent[0] > thr) or audit_gap > audit_tol
+
+        fb_c = None
+        t_fb = 0.0
+        if flagged:  # every bettor: its own Monte-Carlo at the fallback size
+            fbase = (0x20000000 + k * n_bettors) & 0x3FFFFFFF
+            fplan, fprobs, _ = _mc_answers(race, state, n, n_bettors,
+                                           fbase + np.arange(n_bettors), fallback_sims, seed + 3)
+            t_fb = timed(fplan.launch)
+            fb_s += t_fb
+            fplan.free()
+            fb_c = fprobs.cpu().numpy()[:, :n]
+
+        t_base = None
+        if baseline_every and k % baseline_every == 0:  # the plain Monte-Carlo path
+            bbase = (0x30000000 + k * n_bettors) & 0x3FFFFFFF
+            bplan, _, _ = _mc_answers(race, state, n, n_bettors, bbase + np.arange(n_bettors),
+                                      mc_sims, seed + 4)
+            t_base = timed(bplan.launch)
+            bplan.free()
+            base_s += t_base
+            base_q += n_bettors
+
+        jplan, jprobs, _ = _mc_answers(race, state, n, 1, [0x40000000 | k], judge_sims, seed + 2)
         jplan.launch()
         torch.cuda.synchronize()
         jplan.free()
         judge = jprobs.cpu().numpy()[0, :n]
-        # surrogate answers are in slot order; map them back to competitors
-        sl = slot.cpu().numpy()[0]
-        sp = sprobs.cpu().numpy()[0]
-        sur_c = np.zeros(n)
-        for r in range(n):
-            sur_c[sl[r]] = sp[r]
         mc_c = mprobs.cpu().numpy()[:, :n]
         sur_err = float(np.abs(sur_c - judge).max())
         mc_err = float(np.abs(mc_c - judge[None, :]).max())
+        fb_err = float(np.abs(fb_c - judge[None, :]).max()) if flagged else None
         if on_round is not None:
-            on_round(dict(round=len(rounds), state=state, ask=ask, requests=base + ask,
-                          mc_seed=seed + 1, judge_request=0x40000000 | len(rounds),
+            on_round(dict(round=k, state=state, ask=ask, requests=base + ask,
+                          mc_seed=seed + 1, judge_request=0x40000000 | k,
                           judge_seed=seed + 2, mc_probs=mprobs.cpu().numpy(), judge=judge,
                           x=x.cpu().numpy(), slot=slot.cpu().numpy(),
-                          sur_probs=sprobs.cpu().numpy(), entropy=ent, flagged=flagged))
+                          sur_probs=sprobs.cpu().numpy(), entropy=ent, flagged=flagged,
+                          pooled=pooled, audit_gap=audit_gap, fallback=fb_c,
+                          fallback_seed=seed + 3, fallback_base=(0x20000000 + k * n_bettors)
+                          & 0x3FFFFFFF))
         rounds.append(dict(tick=tick, leader=float(pos.max()), entropy=float(ent[0]),
-                           flagged=flagged, mc_queries=int(len(ask)), sur_err=sur_err,
-                           mc_err=mc_err, answer_err=mc_err if flagged else sur_err,
-                           t_sur=t_sur, t_mc=t_mc))
+                           audit_gap=audit_gap, flagged=flagged, sur_err=sur_err, mc_err=mc_err,
+                           fallback_err=fb_err, answer_err=fb_err if flagged else sur_err,
+                           t_sur=t_sur, t_audit=t_audit, t_fallback=t_fb, t_baseline=t_base))
         if len(rounds) % 25 == 0:
             r = rounds[-1]
             log(f"round {len(rounds)} tick {tick} leader {r['leader']:.0f} sur_err "
-                f"{r['sur_err']:.4f} mc_err {r['mc_err']:.4f} flagged {r['flagged']}")
+                f"{r['sur_err']:.4f} audit_gap {audit_gap:.4f} flagged {r['flagged']}")
     sur_err = np.array([r["sur_err"] for r in rounds])
     mc_err = np.array([r["mc_err"] for r in rounds])
     ans_err = np.array([r["answer_err"] for r in rounds])
     n_flag = int(sum(r["flagged"] for r in rounds))
+    served = [r["sur_err"] for r in rounds if not r["flagged"]]
+    fb = [r["fallback_err"] for r in rounds if r["flagged"]]
     total_q = len(rounds) * n_bettors
-    mc_qps = mc_q / mc_s
-    sys_qps = total_q / (sur_s + mc_s)
+    sys_s = sur_s + audit_s + fb_s
+    mc_qps = base_q / base_s if base_s > 0 else float("nan")
+    sys_qps = total_q / sys_s
+
+    def stats(a):
+        a = np.asarray(a, dtype=np.float64)
+        if a.size == 0:
+            return None
+        return dict(max=float(a.max()), mean=float(a.mean()),
+                    p99=float(np.quantile(a, 0.99)), p999=float(np.quantile(a, 0.999)))
     return dict(rounds=len(rounds), bettors=n_bettors, every=every, mc_sims=mc_sims,
-                judge_sims=judge_sims, entropy_threshold=thr, audit_frac=audit_frac,
-                surrogate_queries_per_s=sur_q / sur_s, mc_queries_per_s=mc_qps,
-                speedup=(sur_q / sur_s) / mc_qps,
+                fallback_sims=fallback_sims, judge_sims=judge_sims, entropy_threshold=thr,
+                audit_frac=audit_frac, audit_tol=audit_tol,
+                surrogate_queries_per_s=total_q / sur_s, mc_queries_per_s=mc_qps,
+                speedup=(total_q / sur_s) / mc_qps,
                 system_queries_per_s=sys_qps, system_speedup=sys_qps / mc_qps,
+                seconds=dict(surrogate=sur_s, audit=audit_s, fallback=fb_s,
+                             baseline_sampled=base_s, baseline_rounds=base_q // n_bettors),
                 flagged_rounds=n_flag, served_frac=1.0 - n_flag / max(1, len(rounds)),
-                surrogate_err=dict(max=float(sur_err.max()), mean=float(sur_err.mean()),
-                                   p99=float(np.quantile(sur_err, 0.99)),
-                                   p999=float(np.quantile(sur_err, 0.999))),
-                answer_err=dict(max=float(ans_err.max()), mean=float(ans_err.mean()),
-                                p999=float(np.quantile(ans_err, 0.999))),
-                mc_err=dict(max=float(mc_err.max()), mean=float(mc_err.mean()),
-                            p999=float(np.quantile(mc_err, 0.999))),
+                surrogate_err=stats(sur_err), served_err=stats(served),
+                fallback_err=stats(fb), answer_err=stats(ans_err), mc_err=stats(mc_err),
                 per_round=rounds)
 
 
 def main():
     ap = argparse.ArgumentParser(description="in-play query loop")
-    ap.add_argument("--params", required=True, help="trained surrogate parameters (.npy)")
+    ap.add_argument("--params", required=True,
+                    help="trained surrogate: a saved network (bbe_mlp_save) or parameters (.npy)")
     ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--bettors", type=int, default=10_000)
+    ap.add_argument("--fallback-sims", type=int, default=25_000)
     ap.add_argument("--judge-sims", type=int, default=1_000_000)
+    ap.add_argument("--audit-tol", type=float, default=0.0175)
     ap.add_argument("--max-rounds", type=int, default=None)
-    ap.add_argument("--gate", default=None,
-                    help="surrogate entropy above which a state goes to Monte-Carlo: a number, "
-                         "or 'auto' for the calibrated gate in result.json beside --params "
+    ap.add_argument("--gate", type=float, default=None,
+                    help="surrogate entropy above which a state goes to Monte-Carlo "
                          "(default 0.95 ln n)")
     ap.add_argument("--out", default="bbe_out/query_loop.json")
     args = ap.parse_args()
     torch.cuda.set_device(0)
-    params = np.load(args.params)
-    gate = args.gate
-    if gate == "auto":
-        with open(os.path.join(os.path.dirname(args.params), "result.json")) as f:
-            gate = json.load(f)["gate"]["entropy_threshold"]
+    if args.params.endswith(".npy"):
+        net = np.load(args.params)
+    else:
+        net = _bbe.Mlp.load(args.params, max_batch=8)
     t0 = time.perf_counter()
-    res = run(params, every=args.every, n_bettors=args.bettors, judge_sims=args.judge_sims,
-              gate=None if gate is None else float(gate), max_rounds=args.max_rounds,
-              log=lambda m: print(f"[query] {m}", flush=True))
+    res = run(net, every=args.every, n_bettors=args.bettors, fallback_sims=args.fallback_sims,
+              judge_sims=args.judge_sims, gate=args.gate, audit_tol=args.audit_tol,
+              max_rounds=args.max_rounds, log=lambda m: print(f"[query] {m}", flush=True))
     res["wall_s"] = time.perf_counter() - t0
     summary = {k: v for k, v in res.items() if k != "per_round"}
     print(json.dumps(summary), flush=True)

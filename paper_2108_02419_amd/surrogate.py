@@ -8,7 +8,7 @@ Labels are the frequentist win estimates of the paper's RP(d) bettors
 map from an in-play state to those probabilities and is judged against a
 high-sample Monte-Carlo estimate.
 
-    python -m paper_2108_02419_amd.surrogate --states 200000 --label-sims 2000
+    python -m paper_2108_02419_amd.surrogate --states 10000000 --label-sims 10000
 """
 from __future__ import annotations
 
@@ -110,7 +110,86 @@ def encode(ds: Dataset, probs=None):
     return x, n, slot, target
 
 
-def train(net, x, n, target, epochs: int, batch: int, lr_max: float, log=None):
+class BlockStates:
+    """One block of surrogate states on the GPU (inputs.surrogate_state_block):
+    races, in-play states produced by the model's own runs, and the request
+    table of their Monte-Carlo answers."""
+
+    def __init__(self, block: int, seed: int, count: int = inputs.SURROGATE_BLOCK):
+        a = inputs.surrogate_state_block(block, count)
+        self.block, self.count = block, count
+        self.n = a["n"]
+        self.comp = a["comp"]
+        self.races = [_bbe.Race(a["comp"][i, :a["n"][i]], L) for i in range(count)]
+        dev = torch.device("cuda")
+        tick = torch.empty(count, dtype=torch.int32, device=dev)
+        self.pos_d = torch.empty((count, 20), dtype=torch.float32, device=dev)
+        self.prev_d = torch.empty((count, 20), dtype=torch.float32, device=dev)
+        tab = _bbe.RequestTable(self.races, 1, a["prefix_request"])
+        _bbe.prefix_batch(tab, np.zeros(count, np.uint32), a["target"], seed, tick, self.pos_d,
+                          self.prev_d)
+        torch.cuda.synchronize()
+        self.tick = tick.cpu().numpy().view(np.uint32)
+        if (self.tick == 0xFFFFFFFF).any():
+            raise RuntimeError("an in-play state could not be generated")
+        self.pos = self.pos_d.cpu().numpy()
+        self.prev = self.prev_d.cpu().numpy()
+        self.comp_d = torch.tensor(self.comp, device=dev)
+        self.n_d = torch.tensor(self.n, device=dev)
+
+    def mc(self, n_sims: int, seed: int, request_base: int, stop_after: int = 1):
+        """Monte-Carlo win probabilities (device float64 [count, 20],
+        competitor order) and the competitor-steps simulated."""
+        dev = torch.device("cuda")
+        reqs = (request_base + np.arange(self.count, dtype=np.int64)) & 0x7FFFFFFF
+        tab = _bbe.RequestTable(self.races, n_sims, reqs, stop_after, tick=self.tick,
+                                pos=self.pos, prev=self.prev)
+        wins = torch.zeros((self.count, 20), dtype=torch.int64, device=dev)
+        probs = torch.zeros((self.count, 20), dtype=torch.float64, device=dev)
+        steps = torch.zeros(1, dtype=torch.int64, device=dev)
+        plan = _bbe.BatchPlan(tab, seed, wins, probs, steps)
+        plan.launch()
+        torch.cuda.synchronize()
+        plan.free()
+        return probs, int(steps.item())
+
+    def encode(self, x, slot=None, probs=None, target=None):
+        """Features into x (int16 bits [count, 160]) and, with probs, the
+        slot-ordered targets."""
+        _bbe.encode_states(self.comp_d, self.n_d, self.pos_d, self.prev_d, L, DT, x, slot,
+                           probs, target)
+
+
+def build_training_set(n_states: int, label_sims: int, seed: int, log=None):
+    """n_states training states (blocks 0, 1, ... of the state recipe) with
+    Monte-Carlo labels of label_sims simulations each (winner only), kept on
+    the GPU only: features x int16 [B, 160], n int32 [B], targets float32
+    [B, 20] (slot order).  Returns (x, n, target, competitor-steps, seconds
+    of Monte-Carlo)."""
+    dev = torch.device("cuda")
+    x = torch.empty((n_states, 160), dtype=torch.int16, device=dev)
+    n = torch.empty(n_states, dtype=torch.int32, device=dev)
+    target = torch.empty((n_states, 20), dtype=torch.float32, device=dev)
+    steps_total, mc_s = 0, 0.0
+    t0 = time.perf_counter()
+    for b, lo in enumerate(range(0, n_states, inputs.SURROGATE_BLOCK)):
+        cnt = min(inputs.SURROGATE_BLOCK, n_states - lo)
+        st = BlockStates(b, seed, cnt)
+        t1 = time.perf_counter()
+        probs, steps = st.mc(label_sims, seed, request_base=lo)
+        mc_s += time.perf_counter() - t1
+        steps_total += steps
+        st.encode(x[lo:lo + cnt], None, probs, target[lo:lo + cnt])
+        n[lo:lo + cnt] = st.n_d
+        torch.cuda.synchronize()
+        del st, probs
+        if log and (b % 16 == 15 or lo + cnt == n_states):
+            log(f"labelled {lo + cnt}/{n_states} states ({time.perf_counter() - t0:.0f} s, "
+                f"Monte-Carlo {steps_total / max(mc_s, 1e-9):.3e} competitor-steps/s)")
+    return x, n, target, steps_total, mc_s
+
+
+def train(net, x, n, target, epochs: int, batch: int, lr_max: float, log=None, shuffle_seed=None):
     """Adam over contiguous minibatches (the dataset is generated in a
     random order); learning rate: linear warm-up over the first epoch, then
     cosine decay to lr_max/100."""
@@ -121,10 +200,14 @@ def train(net, x, n, target, epochs: int, batch: int, lr_max: float, log=None):
     hist = []
     step = 0
     t0 = time.perf_counter()
+    rng = np.random.default_rng(shuffle_seed) if shuffle_seed is not None else None
     for ep in range(epochs):
         ep_loss = 0.0
+        # minibatch order: contiguous blocks, in a fresh random order per
+        # epoch when shuffle_seed is given
+        order = rng.permutation(n_batches) if rng is not None else range(n_batches)
         for b in range(n_batches):
-            lo = b * batch
+            lo = int(order[b]) * batch
             frac = step / max(1, total - 1)
             warm = min(1.0, (step + 1) / n_batches)
             lr = lr_max * warm * (0.01 + 0.99 * 0.5 * (1 + np.cos(np.pi * frac)))
@@ -200,72 +283,88 @@ def gated_errors(pred_slot, ent, mc_slot, ref_slot, n, gate):
                 answer_max_err=float(ans.max()), surrogate_max_err=float(es.max()))
 
 
+EVAL_BLOCK0 = 4096  # held-out states come from blocks 4096, 4097, ... (training: 0, 1, ...)
+
+
+def build_eval_set(n_states: int, judge_sims: int, seed: int, fallback_sims=(10_000,),
+                   rp_sims=(), block0: int = EVAL_BLOCK0):
+    """Held-out states with a high-sample Monte-Carlo judge and, for each
+    entry of fallback_sims and rp_sims, Monte-Carlo answers of that many
+    simulations (the fallback's and RP(d) bettors' own answers).  Device
+    tensors: x, n, judge (slot order), answers {sims: slot-ordered}."""
+    dev = torch.device("cuda")
+    xs, ns, js = [], [], []
+    ans = {d: [] for d in tuple(fallback_sims) + tuple(rp_sims)}
+    for b, lo in enumerate(range(0, n_states, inputs.SURROGATE_BLOCK)):
+        cnt = min(inputs.SURROGATE_BLOCK, n_states - lo)
+        st = BlockStates(block0 + b, seed, cnt)
+        x = torch.empty((cnt, 160), dtype=torch.int16, device=dev)
+        jt = torch.empty((cnt, 20), dtype=torch.float32, device=dev)
+        jp, _ = st.mc(judge_sims, seed + 1, request_base=(1 << 24) + lo)
+        st.encode(x, None, jp, jt)
+        for d in ans:
+            dp, _ = st.mc(d, seed + 2, request_base=(1 << 25) + (d << 12) + lo)
+            t = torch.empty((cnt, 20), dtype=torch.float32, device=dev)
+            st.encode(torch.empty_like(x), None, dp, t)
+            ans[d].append(t)
+        xs.append(x)
+        ns.append(st.n_d.clone())
+        js.append(jt)
+        torch.cuda.synchronize()
+    return (torch.cat(xs), torch.cat(ns), torch.cat(js),
+            {d: torch.cat(v) for d, v in ans.items()})
+
+
 def train_and_judge(states=200_000, label_sims=2000, epochs=30, batch=4096, lr=2e-3, seed=4,
                     eval_states=2000, judge_sims=1_000_000, target_err=0.02, rp_sims=(4, 16, 64),
-                    log=None):
+                    fallback_sims=(10_000,), log=None):
     """Generates states and Monte-Carlo labels, trains a network, judges it
-    on held-out states and calibrates its Monte-Carlo fallback gate.
-    Returns (network, result dict)."""
+    on held-out states and calibrates its Monte-Carlo fallback gate (on the
+    first half of the held-out states; tested on the second half, with each
+    fallback size of fallback_sims).  Returns (network, result dict)."""
     log = log or (lambda m: None)
-    t0 = time.perf_counter()
-    specs = inputs.surrogate_states(states)
-    rng = np.random.default_rng(seed)
-    specs = [specs[i] for i in rng.permutation(len(specs))]
-    ds = gen_states(specs, seed)
-    log(f"{len(ds)} training states ({time.perf_counter() - t0:.1f} s)")
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    probs, steps = mc_probs(ds, label_sims, seed, request_base=0)
-    ev1.record()
-    torch.cuda.synchronize()
-    label_s = ev0.elapsed_time(ev1) / 1e3
-    log(f"labels: {len(ds)} x {label_sims} sims, {steps} competitor-steps, {label_s:.1f} s "
+    x, n, target, steps, label_s = build_training_set(states, label_sims, seed, log)
+    log(f"labels: {states} x {label_sims} sims, {steps} competitor-steps, {label_s:.1f} s "
         f"({steps / label_s:.3e} competitor-steps/s)")
-    x, n, _, target = encode(ds, probs)
     net = _bbe.Mlp(inputs.surrogate_init(seed), max_batch=batch)
     t1 = time.perf_counter()
-    hist = train(net, x, n, target, epochs, batch, lr, log)
+    hist = train(net, x, n, target, epochs, batch, lr, log, shuffle_seed=seed)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
+    del x, target
 
-    # held-out states judged by high-sample Monte-Carlo
-    espec = inputs.surrogate_states(eval_states, first=10_000_000)
-    eds = gen_states(espec, seed + 1)
-    jprobs, _ = mc_probs(eds, judge_sims, seed + 1, request_base=1 << 24)
-    ex, en, _, jt = encode(eds, jprobs)
+    ex, en, jt, ans = build_eval_set(eval_states, judge_sims, seed, fallback_sims, rp_sims)
     pred, ent = predict(net, ex, en)
-    rp = {}
-    for d in tuple(rp_sims) + (10_000,):  # RP(d) bettors: d simulations each
-        dprobs, _ = mc_probs(eds, d, seed + 2, request_base=(1 << 25) + d)
-        rp[d] = encode(eds, dprobs)[3]
     torch.cuda.synchronize()
-    half = len(eds) // 2
+    half = eval_states // 2
     gate = calibrate_gate(pred[:half], ent[:half], jt[:half], en[:half], target_err)
-    res = dict(train_states=len(ds), label_sims=label_sims, epochs=epochs, batch=batch, lr=lr,
+    res = dict(train_states=states, label_sims=label_sims, epochs=epochs, batch=batch, lr=lr,
                train_seconds=train_s, label_seconds=label_s, label_competitor_steps=steps,
-               loss_history=hist, eval_states=len(eds), judge_sims=judge_sims,
+               loss_history=hist, eval_states=eval_states, judge_sims=judge_sims,
                surrogate_vs_judge=errors(pred, jt, en),
-               **{f"rp{d}_vs_judge": errors(v, jt, en) for d, v in rp.items()},
+               **{f"mc{d}_vs_judge": errors(v, jt, en) for d, v in ans.items()},
                gate=dict(target_err=target_err, entropy_threshold=gate,
                          calibration_states=half,
-                         test=gated_errors(pred[half:], ent[half:], rp[10_000][half:],
-                                           jt[half:], en[half:], gate)))
+                         test={str(d): gated_errors(pred[half:], ent[half:], ans[d][half:],
+                                                    jt[half:], en[half:], gate)
+                               for d in fallback_sims}))
     return net, res
 
 
 def main():
     ap = argparse.ArgumentParser(description="train and judge the surrogate")
-    ap.add_argument("--states", type=int, default=200_000)
-    ap.add_argument("--label-sims", type=int, default=2000)
+    ap.add_argument("--states", type=int, default=10_000_000)
+    ap.add_argument("--label-sims", type=int, default=10_000)
     ap.add_argument("--eval-states", type=int, default=2000,
                     help="held-out states: first half calibrates the gate, second half tests it")
     ap.add_argument("--target-err", type=float, default=0.02)
     ap.add_argument("--judge-sims", type=int, default=1_000_000)
-    ap.add_argument("--epochs", type=int, default=30)
-    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--epochs", type=int, default=150)
+    ap.add_argument("--batch", type=int, default=2048)
     ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--seed", type=int, default=4)
+    ap.add_argument("--fallback-sims", type=int, nargs="+", default=[10_000, 25_000],
+                    help="Monte-Carlo fallback sizes the gate is tested with")
     ap.add_argument("--out", default="bbe_out/surrogate")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
@@ -276,9 +375,10 @@ def main():
     torch.cuda.set_device(0)
     net, res = train_and_judge(args.states, args.label_sims, args.epochs, args.batch, args.lr,
                                args.seed, args.eval_states, args.judge_sims, args.target_err,
-                               log=log)
+                               fallback_sims=tuple(args.fallback_sims), log=log)
     log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
     np.save(os.path.join(args.out, "params.npy"), net.params())
+    net.save(os.path.join(args.out, "surrogate.bbemlp"))
     with open(os.path.join(args.out, "result.json"), "w") as f:
         json.dump(res, f, indent=1)
 

@@ -141,22 +141,25 @@ def _slot_to_comp(sp, slot, n):
     return out
 
 
-@pytest.mark.parametrize("gate", [-1.0, 1e9], ids=["all-to-mc", "audit-only"])
+@pytest.mark.parametrize("gate", [-1.0, 1e9], ids=["fallback", "served"])
 def test_query_loop_end_to_end(torch, orc, gate):
-    """Three rounds, 7 ticks apart, 300 bettors: the watched race, sampled
-    Monte-Carlo answers and the judge against the oracle bit for bit, the
+    """Three rounds, 7 ticks apart, 300 bettors: the watched race, the 1%
+    audit's Monte-Carlo answers and their pooled estimate, the fallback's
+    answers (sampled) and the judge against the oracle bit for bit, the
     surrogate's inputs bit for bit and its answers against the reference
-    network.  gate -1 sends every bettor to Monte-Carlo; 1e9 leaves only the
-    1% audit sample."""
+    network.  gate -1 sends every round to the fallback; 1e9 (with an audit
+    tolerance of 1) serves every round from the surrogate."""
     q = inputs.query_race()
     comp, seed, real = q["comp"], q["seed"], q["real_request"]
     n = comp.shape[0]
     params = inputs.surrogate_random(8)
     rounds = []
     announce(f"query loop gate={gate}")
-    res = query_loop.run(params, every=7, n_bettors=300, mc_sims=400, judge_sims=3000,
-                         gate=gate, max_rounds=3, log=lambda m: None, on_round=rounds.append)
+    res = query_loop.run(params, every=7, n_bettors=300, mc_sims=400, fallback_sims=300,
+                         judge_sims=3000, gate=gate, audit_tol=1.0, baseline_every=2,
+                         max_rounds=3, log=lambda m: None, on_round=rounds.append)
     assert res["rounds"] == 3 and len(rounds) == 3
+    assert res["flagged_rounds"] == (3 if gate < 0 else 0)
     trace = orc.race_trace(comp, L, seed, real, 0, 40)
     rng = np.random.default_rng(4)
     comp_b = np.zeros((1, 20, 5), np.float32)
@@ -167,15 +170,17 @@ def test_query_loop_end_to_end(torch, orc, gate):
         assert tick == want[0] == 7 * (k + 1)
         np.testing.assert_array_equal(pos, want[1])
         np.testing.assert_array_equal(prev, want[2])
-        # Monte-Carlo answers: each asked bettor's own request
+        # the audit: 1% of the bettors, each its own request, pooled
         ask, reqs, mp = rd["ask"], rd["requests"], rd["mc_probs"]
-        assert rd["flagged"] == (gate < 0)
-        assert len(ask) == (300 if gate < 0 else 3)
-        for j in sorted(set(rng.choice(len(ask), min(4, len(ask)), replace=False).tolist())):
+        assert len(ask) == 3 and rd["flagged"] == (gate < 0)
+        pooled = np.zeros(n, np.uint64)
+        for j in range(len(ask)):
             _, w, _ = orc.race_sim(comp, L, 400, rd["mc_seed"], request=int(reqs[j]),
                                    state=rd["state"], stop_after=1, want_orders=False,
                                    threads=8)
             np.testing.assert_array_equal(mp[j, :n], orc.win_probs(w))
+            pooled += w
+        np.testing.assert_array_equal(rd["pooled"], orc.win_probs(pooled))
         _, wj, _ = orc.race_sim(comp, L, 3000, rd["judge_seed"], request=rd["judge_request"],
                                 state=rd["state"], stop_after=1, want_orders=False, threads=8)
         np.testing.assert_array_equal(rd["judge"], orc.win_probs(wj))
@@ -190,8 +195,25 @@ def test_query_loop_end_to_end(torch, orc, gate):
         _, qref, _ = ref.forward(params.astype(np.float64), ref.bf16(X), [n])
         np.testing.assert_allclose(sp[0], qref[0], atol=2e-3)
         assert abs(rd["entropy"][0] - ref.entropy(qref)[0]) <= 5e-3
-        # the loop's own error figures are those of these answers
         sur_c = _slot_to_comp(sp[0], slot[0], n)
-        assert np.isclose(res["per_round"][k]["sur_err"], np.abs(sur_c - rd["judge"]).max())
-        assert np.isclose(res["per_round"][k]["mc_err"],
-                          np.abs(mp[:, :n] - rd["judge"][None, :]).max())
+        assert np.isclose(rd["audit_gap"], np.abs(sur_c - rd["pooled"]).max())
+        # the fallback (flagged rounds): every bettor its own request; sampled
+        if gate < 0:
+            fb = rd["fallback"]
+            assert fb.shape == (300, n)
+            for i in sorted(set(rng.choice(300, 3, replace=False).tolist())):
+                _, w, _ = orc.race_sim(comp, L, 300, rd["fallback_seed"],
+                                       request=int(rd["fallback_base"] + i), state=rd["state"],
+                                       stop_after=1, want_orders=False, threads=8)
+                np.testing.assert_array_equal(fb[i], orc.win_probs(w))
+        else:
+            assert rd["fallback"] is None
+        # the loop's own error figures are those of these answers
+        pr = res["per_round"][k]
+        assert np.isclose(pr["sur_err"], np.abs(sur_c - rd["judge"]).max())
+        assert np.isclose(pr["mc_err"], np.abs(mp[:, :n] - rd["judge"][None, :]).max())
+        if gate < 0:
+            assert np.isclose(pr["answer_err"], np.abs(rd["fallback"] - rd["judge"][None, :]).max())
+        else:
+            assert pr["answer_err"] == pr["sur_err"]
+    assert res["seconds"]["baseline_rounds"] == 2  # rounds 0 and 2

@@ -200,10 +200,16 @@ def test_adam_matches_reference(torch):
     np.testing.assert_allclose(got, p, rtol=1e-6, atol=1e-9)
 
 
-def test_encoder_bit_exact(torch):
-    reqs = inputs.surrogate_states(64)
+@pytest.mark.parametrize("B", [64, 37])
+def test_encoder_bit_exact(torch, B):
+    """Two states per wave: an even batch and a ragged one (the last wave's
+    second half holds no state); exact position ties and a one-competitor
+    state exercise the slot order."""
+    reqs = inputs.surrogate_states(B)
+    reqs[7] = inputs.RequestSpec(index=7, comp=reqs[7].comp[:1], remaining=reqs[7].remaining,
+                                 target=reqs[7].target, n_sims=reqs[7].n_sims,
+                                 prefix_request=reqs[7].prefix_request)
     import oracle
-    B = len(reqs)
     comp = np.zeros((B, 20, 5), np.float32)
     pos = np.zeros((B, 20), np.float32)
     prev = np.zeros((B, 20), np.float32)
@@ -214,15 +220,20 @@ def test_encoder_bit_exact(torch):
         pos[i, :r.n], prev[i, :r.n] = p, q
     pos[5, :3] = pos[5, 3]  # exact ties exercise the slot order
     X, slot = ref.encode(comp, n, pos, prev, inputs.TRACK_LEN, 0.1)
-    x = torch.empty((B, 160), dtype=torch.int16, device="cuda")
-    s = torch.empty((B, 20), dtype=torch.int32, device="cuda")
+    x = torch.full((B, 160), 77, dtype=torch.int16, device="cuda")
+    s = torch.full((B, 20), 77, dtype=torch.int32, device="cuda")
+    probs = np.random.default_rng(B).random((B, 20))
+    tgt = torch.full((B, 20), 7.0, dtype=torch.float32, device="cuda")
     _bbe.encode_states(torch.tensor(comp, device="cuda"), torch.tensor(n, device="cuda"),
                        torch.tensor(pos, device="cuda"), torch.tensor(prev, device="cuda"),
-                       inputs.TRACK_LEN, 0.1, x, s)
+                       inputs.TRACK_LEN, 0.1, x, s, torch.tensor(probs, device="cuda"), tgt)
     torch.cuda.synchronize()
     want = (ref.bf16(X).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
     np.testing.assert_array_equal(x.cpu().numpy().view(np.uint16), want)
     np.testing.assert_array_equal(s.cpu().numpy(), slot)
+    # labels follow the slots: target[b][r] = probs[b][competitor in slot r], 0 in padding
+    want_t = np.where(slot >= 0, np.take_along_axis(probs, np.maximum(slot, 0), axis=1), 0.0)
+    np.testing.assert_array_equal(tgt.cpu().numpy(), want_t.astype(np.float32))
 
 
 def test_training_reduces_loss(torch):
