@@ -478,15 +478,16 @@ int bbe_mlp_train_step(bbe_mlp *m, const uint16_t *x, const int32_t *n_valid,
 /* Encodes in-play states for the network.  Device inputs: comp float
  * [batch][20][5] (lo, hi, pref, rho, theta per competitor), n int32
  * [batch] (competitors, 1..20), pos and prev float [batch][20] (state, as
- * in bbe_state).  Slots list the competitors by position, leader first
- * (equal positions: lower index first), padded to 20; per slot 8 float32
- * features rounded to bfloat16, positions only relative to the line or to
- * other competitors: (L-d)/L, (d_lead-d)/(75 dt), min((d_above-d)/(7.5 dt),
- * 4) (4 for the leader), s/(7.5 dt), (lo+hi)/(15 dt), (hi-lo)/(hi+lo),
- * rho/0.2 and (T - T_min)/10 with T = (L-d)/((lo+hi)*0.5*(1 + rho*d/L))
- * the expected remaining ticks and T_min the state's smallest (all 0 for
- * padding), where dt is the tick length in seconds the race parameters are
- * expressed in.  Outputs: x [batch][160] (16-byte aligned, else
+ * in bbe_state).  Slots list the competitors by expected remaining ticks
+ * T = (L-d)/((lo+hi)*0.5*(1 + rho*d/L)), smallest first (equal T: lower
+ * index first), padded to 20; per slot 8 float32 features rounded to
+ * bfloat16, positions only relative to the line or to other competitors:
+ * (L-d)/L, (d_lead-d)/(75 dt), min((d_above-d)/(7.5 dt), 4) with d_above
+ * the position of the competitor directly ahead on the track (position
+ * order, equal positions by lower index; 4 for the leader), s/(7.5 dt),
+ * (lo+hi)/(15 dt), (hi-lo)/(hi+lo), rho/0.2 and (T - T_min)/10 with T_min
+ * the state's smallest T (all 0 for padding), where dt is the tick length
+ * in seconds the race parameters are expressed in.  Outputs: x [batch][160] (16-byte aligned, else
  * BBE_EINVAL); slot_comp int32 [batch][20] or
  * NULL, the competitor in each slot (-1 for padding).  With probs (device
  * double [batch][20], competitor order, e.g. from bbe_batch_plan_create)

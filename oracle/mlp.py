@@ -171,14 +171,18 @@ def encode(comp, n, pos, prev, track_len, dt):
     """Features [B, 160] (float32, before bfloat16 rounding) and the
     competitor index in each slot [B, 20] (-1 for padding).
 
-    Slots hold the competitors by position, leader first (equal positions:
-    lower index first), padded to 20.  Positions enter only as distances
-    relative to other competitors or to the line, so that bfloat16 keeps
-    the gaps that decide a race.  Per slot 8 features, each one float32
-    operation sequence (v = fl(7.5 dt), w = fl(75 dt), c15 = fl(15 dt)):
+    Slots hold the competitors by expected remaining ticks T (below),
+    smallest first (equal T: lower index first), padded to 20: early in a
+    race that orders the field by strength, late in it by position.
+    Positions enter only as distances relative to other competitors or to
+    the line, so that bfloat16 keeps the gaps that decide a race.  Per slot
+    8 features, each one float32 operation sequence (v = fl(7.5 dt),
+    w = fl(75 dt), c15 = fl(15 dt)):
       1 rem  = (L-d)/L                       remaining distance
-      2 lead = (d_lead - d)/w                gap to the leader
-      3 gap  = min((d_up - d)/v, 4)          gap to the slot above (4 for the leader)
+      2 lead = (d_lead - d)/w                gap to the leader on the track
+      3 gap  = min((d_up - d)/v, 4)          gap to the competitor directly ahead on
+                                             the track (position order, equal
+                                             positions by index; 4 for the leader)
       4 s/v                                  previous step
       5 spd  = (lo+hi)/c15                   mean free step over 7.5 dt
       6 (hi-lo)/(hi+lo)                      relative noise
@@ -199,19 +203,21 @@ def encode(comp, n, pos, prev, track_len, dt):
     slot = np.full((B, 20), -1, dtype=np.int32)
     for b in range(B):
         k = int(n[b])
-        order = sorted(range(k), key=lambda c: (-float(pos[b][c]), c))
+        by_pos = sorted(range(k), key=lambda c: (-float(pos[b][c]), c))  # the track, leader first
         T = []
         for c in range(k):
             lo, hi, _, rho, _ = comp[b, c]
             d = f(pos[b][c])
             rmid = f(f(1.0) + f(rho * f(d / L)))
             T.append(f(f(L - d) / f(f(f(lo + hi) * f(0.5)) * rmid)))
+        order = sorted(range(k), key=lambda c: (float(T[c]), c))
         t_min = min(T) if T else f(0.0)
-        d_lead = f(pos[b][order[0]]) if k else f(0.0)
+        d_lead = f(pos[b][by_pos[0]]) if k else f(0.0)
         for r, c in enumerate(order):
             lo, hi, _, rho, _ = comp[b, c]
             d, s = f(pos[b][c]), f(prev[b][c])
-            gap = f(4.0) if r == 0 else min(f(f(f(pos[b][order[r - 1]]) - d) / v), f(4.0))
+            q = by_pos.index(c)  # its place on the track
+            gap = f(4.0) if q == 0 else min(f(f(f(pos[b][by_pos[q - 1]]) - d) / v), f(4.0))
             X[b, r] = [f(f(L - d) / L), f(f(d_lead - d) / w), gap, f(s / v),
                        f(f(lo + hi) / c15), f(f(hi - lo) / f(hi + lo)), f(rho / f(0.2)),
                        f(f(T[c] - t_min) / f(10.0))]

@@ -231,13 +231,17 @@ __global__ void __launch_bounds__(256) mlp_bwd_data_kernel(const MlpBwdArgs a) {
     }
 }
 
-// Weight gradients dW[n][k] = sum over the batch rows of dz[r][n] * h[r][k].
+// Weight gradients dW[n][k] = sum over the batch rows of dz[r][n] * h[r][k],
+// and bias gradients db[n] = sum over the rows of dz[r][n].
 // One workgroup: a 64 (n) x 64 (k) tile of one layer over one chunk of
 // kWgRows rows (blockIdx.y); it stores its tile once -- into the gradient
 // itself when the batch is one chunk, else into that chunk's partial
-// vector, which mlp_wreduce_kernel sums in chunk order.  No atomics, so the
-// gradient (and training) is the same bit for bit from run to run.  Both
-// operands are staged transposed in LDS so that fragments are contiguous.
+// vector, which mlp_wreduce_kernel sums in chunk order.  The tile at k0 = 0
+// also sums its 64 dz columns over the chunk (each wave a quarter of the
+// rows in order, the quarters added in wave order) for the bias gradient.
+// No atomics, so the gradient (and training) is the same bit for bit from
+// run to run.  Both operands are staged transposed in LDS so that fragments
+// are contiguous.
 constexpr int kWgS = kWgRows + 8;
 
 __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const MlpWgradArgs a) {
@@ -279,48 +283,45 @@ __global__ void __launch_bounds__(256) mlp_wgrad_kernel(const MlpWgradArgs a) {
             if (n < L.n_rows && k < L.K) out[(size_t)n * L.K + k] = acc[cb][i];
         }
     }
+    if (t.k0 == 0) {  // uniform per workgroup
+        __shared__ float bpart[4][64];
+        constexpr int kQ = kWgRows / 4;
+        float sum = 0.0f;
+        const uint16_t* col = tz + lane * kWgS + wave * kQ;
+        for (int r = 0; r < kQ; ++r) sum += from_bf16(col[r]);
+        bpart[wave][lane] = sum;
+        __syncthreads();
+        const int n = t.n0 + lane;
+        if (wave == 0 && n < L.n_rows) {
+            const float b = ((bpart[0][lane] + bpart[1][lane]) + bpart[2][lane]) + bpart[3][lane];
+            if (gridDim.y == 1)
+                L.gb[n] = b;
+            else
+                a.part[(size_t)blockIdx.y * kNParams + L.woff + L.n_rows * L.K + n] = b;
+        }
+    }
 }
 
-// Sum of the per-chunk partial weight gradients, chunk 0 first: one thread
-// per weight of the four layers.
+// Sum of the per-chunk partial gradients (weights and biases), chunk 0
+// first: one thread per parameter of the four layers (each layer's weights
+// then its bias, as packed).
 __global__ void __launch_bounds__(256) mlp_wreduce_kernel(const MlpWgradArgs a, int n_chunks) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
 #pragma unroll
     for (int l = 0; l < 4; ++l) {
         const LayerGrad& L = a.layers[l];
-        const int size = L.n_rows * L.K;
-        if (i < size) {
+        const int nw = L.n_rows * L.K;
+        if (i < nw + L.n_rows) {
             const float* p = a.part + L.woff + i;
             float s = p[0];
             for (int c = 1; c < n_chunks; ++c) s += p[(size_t)c * kNParams];
-            L.gw[i] = s;
+            if (i < nw)
+                L.gw[i] = s;
+            else
+                L.gb[i - nw] = s;
             return;
         }
-        i -= size;
-    }
-}
-
-// Bias gradients: db[n] = sum_r dz[r][n]; one workgroup per 64 columns of a
-// layer, rows strided over its kBgWaves waves, whose partial sums are added
-// in wave order (fixed, so the result is the same on every call).
-constexpr int kBgWaves = 16;
-
-__global__ void __launch_bounds__(64 * kBgWaves) mlp_bgrad_kernel(const MlpWgradArgs a) {
-    __shared__ float part[kBgWaves][64];
-    const int layer = blockIdx.y;
-    const LayerGrad& L = a.layers[layer];
-    const int lane = threadIdx.x & 63;
-    const int n = blockIdx.x * 64 + lane;
-    const int w = threadIdx.x >> 6;
-    float s = 0.0f;
-    if (n < L.n_rows)
-        for (int r = w; r < a.B; r += kBgWaves) s += from_bf16(L.dz[(size_t)r * L.dz_stride + n]);
-    part[w][lane] = s;
-    __syncthreads();
-    if (w == 0 && n < L.n_rows) {
-        float t = part[0][lane];
-        for (int j = 1; j < kBgWaves; ++j) t += part[j][lane];
-        L.gb[n] = t;
+        i -= nw + L.n_rows;
     }
 }
 
@@ -362,19 +363,21 @@ __global__ void mlp_adam_kernel(const MlpAdamArgs a) {
 }
 
 // State encoding: one state per half-wave (32 lanes), lane c of the half
-// for competitor c.  Slots hold competitors by position, leader first
-// (equal positions: lower index first): a competitor's slot is the number
-// of competitors ahead of it in that order.  Positions enter only relative
-// to other competitors or to the line (bfloat16 keeps about 2.5
-// significant digits: an absolute position would lose the gaps that decide
-// a race).  8 float32 features per slot, rounded to bfloat16: remaining
-// distance (L-d)/L, gap to the leader / (75 dt), gap to the slot above /
-// (7.5 dt) capped at 4 (4 for the leader), previous step / (7.5 dt), mean
-// free step (lo+hi)/(15 dt), (hi-lo)/(hi+lo), rho/0.2, and (T - T_min)/10
-// with T = (L-d) / ((lo+hi)*0.5 * (1 + rho*d/L)) the expected remaining
-// ticks (R_c taken at the midpoint of the remaining distance); zero
-// padding.  Each lane writes its slot's 8 features as one 16-byte store,
-// so a state's 320-byte row is written by 20 adjacent stores.
+// for competitor c.  Slots hold competitors by expected remaining ticks
+// T = (L-d) / ((lo+hi)*0.5 * (1 + rho*d/L)) (R_c taken at the midpoint of
+// the remaining distance), smallest first, equal T by lower index: a
+// competitor's slot is the number of competitors before it in that order.
+// Early in a race that orders the field by strength, late in it by
+// position.  Positions enter only relative to other competitors or to the
+// line (bfloat16 keeps about 2.5 significant digits: an absolute position
+// would lose the gaps that decide a race).  8 float32 features per slot,
+// rounded to bfloat16: remaining distance (L-d)/L, gap to the leader /
+// (75 dt), gap to the competitor directly ahead on the track (position
+// order, equal positions by lower index) / (7.5 dt) capped at 4 (4 for the
+// leader), previous step / (7.5 dt), mean free step (lo+hi)/(15 dt),
+// (hi-lo)/(hi+lo), rho/0.2, and (T - T_min)/10; zero padding.  Each lane
+// writes its slot's 8 features as one 16-byte store, so a state's 320-byte
+// row is written by 20 adjacent stores.
 __global__ void __launch_bounds__(256) encode_kernel(const EncodeArgs a) {
     const int lane = threadIdx.x & 63;
     const int half = lane & 32;                // first lane of this state's half-wave
@@ -395,18 +398,21 @@ __global__ void __launch_bounds__(256) encode_kernel(const EncodeArgs a) {
     }
     const float rmid = 1.0f + rho * (d / L);
     const float T = act ? (L - d) / (((lo + hi) * 0.5f) * rmid) : __builtin_inff();
-    // slot = competitors ahead; the slot above's position; the leader's
-    // position; the smallest expected remaining time
+    // slot = competitors before this one in (T, index) order; the position
+    // of the competitor directly ahead on the track; the leader's position;
+    // the smallest expected remaining time
     int slot = 0;
+    bool has_ahead = false;
     float d_above = __builtin_inff(), d_lead = -__builtin_inff(), tmin = __builtin_inff();
     // every lane runs all kMaxN steps (the two halves may hold different n)
     for (int i = 0; i < kMaxN; ++i) {
         const float di = __shfl(d, half + i, 64);
         const float Ti = __shfl(T, half + i, 64);
         const bool valid = i < n;
+        slot += (valid && (Ti < T || (Ti == T && i < c))) ? 1 : 0;
+        // directly ahead: the lowest of those ahead in (position, index) order
         const bool ahead = valid && (di > d || (di == d && i < c));
-        slot += ahead ? 1 : 0;
-        // the slot above is the lowest of those ahead in (position, index) order
+        has_ahead = has_ahead || ahead;
         d_above = ahead ? fminf(d_above, di) : d_above;
         d_lead = valid ? fmaxf(d_lead, di) : d_lead;
         tmin = valid ? fminf(tmin, Ti) : tmin;
@@ -414,7 +420,7 @@ __global__ void __launch_bounds__(256) encode_kernel(const EncodeArgs a) {
     if (!in || c >= kMaxN) return;
     uint16_t* x = a.x + b * kIn;
     if (act) {
-        const float gap = slot == 0 ? 4.0f : fminf((d_above - d) / a.c75, 4.0f);
+        const float gap = has_ahead ? fminf((d_above - d) / a.c75, 4.0f) : 4.0f;
         const float f[8] = {(L - d) / L,     (d_lead - d) / a.c750, gap,
                             s / a.c75,       (lo + hi) / a.c15,     (hi - lo) / (hi + lo),
                             rho / 0.2f,      (T - tmin) / 10.0f};
@@ -455,13 +461,11 @@ hipError_t launch_mlp_wgrad(const MlpWgradArgs& a, int n_tiles, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if (n_chunks > 1) {
-        constexpr int kWeights = kHid * kIn + 2 * kHid * kHid + kOut * kHid;
-        hipLaunchKernelGGL(mlp_wreduce_kernel, dim3((kWeights + 255) / 256), dim3(256), 0, s, a,
+        hipLaunchKernelGGL(mlp_wreduce_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, a,
                            n_chunks);
-        if ((e = hipGetLastError()) != hipSuccess) return e;
+        e = hipGetLastError();
     }
-    hipLaunchKernelGGL(mlp_bgrad_kernel, dim3(kHid / 64, 4), dim3(64 * kBgWaves), 0, s, a);
-    return hipGetLastError();
+    return e;
 }
 hipError_t launch_mlp_adam(const MlpAdamArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(mlp_adam_kernel, dim3((kNParams + 255) / 256), dim3(256), 0, s, a);

@@ -203,8 +203,9 @@ def test_adam_matches_reference(torch):
 @pytest.mark.parametrize("B", [64, 37])
 def test_encoder_bit_exact(torch, B):
     """Two states per wave: an even batch and a ragged one (the last wave's
-    second half holds no state); exact position ties and a one-competitor
-    state exercise the slot order."""
+    second half holds no state); exact position ties, two identical
+    competitors side by side (equal expected times) and a one-competitor
+    state exercise the slot order and the gap feature."""
     reqs = inputs.surrogate_states(B)
     reqs[7] = inputs.RequestSpec(index=7, comp=reqs[7].comp[:1], remaining=reqs[7].remaining,
                                  target=reqs[7].target, n_sims=reqs[7].n_sims,
@@ -219,6 +220,8 @@ def test_encoder_bit_exact(torch, B):
         t, p, q = oracle.race_prefix(r.comp, inputs.TRACK_LEN, 4, r.prefix_request, 0, r.target)
         pos[i, :r.n], prev[i, :r.n] = p, q
     pos[5, :3] = pos[5, 3]  # exact ties exercise the slot order
+    if reqs[9].n >= 2:  # two identical competitors side by side: equal T, index order
+        comp[9, 1], pos[9, 1], prev[9, 1] = comp[9, 0], pos[9, 0], prev[9, 0]
     X, slot = ref.encode(comp, n, pos, prev, inputs.TRACK_LEN, 0.1)
     x = torch.full((B, 160), 77, dtype=torch.int16, device="cuda")
     s = torch.full((B, 20), 77, dtype=torch.int32, device="cuda")

@@ -94,7 +94,7 @@ def test_encoding_by_hand_and_label_invariance():
     pos[0, :3] = [1000, 1500, 1000]
     prev[0, :3] = [0.75, 0.6, 0.5]
     X, slot = mlp.encode(comp, [3], pos, prev, 2000.0, 0.1)
-    assert slot[0, :4].tolist() == [1, 0, 2, -1]  # leader first, tie by index
+    assert slot[0, :4].tolist() == [1, 0, 2, -1]  # smallest expected remaining ticks first
     f = X.reshape(20, 8)
     # worked by hand (dt = 0.1: step scale 0.75, leader-gap scale 7.5, speed scale 1.5);
     # remaining ticks T = (L-d) / (mean step * (1 + rho*d/L)):
@@ -108,6 +108,23 @@ def test_encoding_by_hand_and_label_invariance():
     ])
     np.testing.assert_allclose(f[:3], want, rtol=2e-6, atol=1e-7)
     assert (f[3:] == 0).all()
+    # slots follow the expected remaining ticks, not the track: a faster
+    # competitor just behind takes slot 0; its gap is to the one ahead on
+    # the track, whose own gap is the leader's 4
+    c2 = np.zeros((1, 20, 5), np.float32)
+    c2[0, :2] = [[4, 6, 1, 0, 2], [8, 10, 1, 0, 2]]
+    p2 = np.zeros((1, 20), np.float32)
+    p2[0, :2] = [1000, 999]
+    s2 = np.zeros((1, 20), np.float32)
+    s2[0, :2] = [0.5, 0.9]
+    X2, sl2 = mlp.encode(c2, [2], p2, s2, 2000.0, 0.1)
+    assert sl2[0, :3].tolist() == [1, 0, -1]
+    # T: c1 1001 / 9 = 111.2222, c0 1000 / 5 = 200
+    want2 = np.array([
+        [0.5005, 1 / 7.5, 1 / 0.75, 1.2,      12.0,    1 / 9., 0.0, 0.0],
+        [0.5,    0.0,     4.0,      0.666667, 6.666667, 0.2,   0.0, 8.8777778],
+    ])
+    np.testing.assert_allclose(X2.reshape(20, 8)[:2], want2, rtol=2e-6, atol=1e-6)
     # relabelling the competitors changes nothing in the encoding (no ties:
     # tied competitors are ordered by index, and the gap feature follows it)
     pos[0, 2] = 900.0
