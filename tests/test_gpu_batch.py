@@ -209,3 +209,62 @@ def test_plan_set_states_equals_fresh_plan(torch, orc):
     plan.launch()
     torch.cuda.synchronize()
     assert torch.equal(wins, got_w) and torch.equal(steps, got_s)
+
+
+_TUNE_CHILD = r"""
+import json, sys
+import numpy as np
+import torch
+sys.path.insert(0, sys.argv[1])
+from paper_2108_02419_amd import _bbe, inputs
+torch.cuda.set_device(0)
+reqs = inputs.batch_requests(n_requests=64)
+races = [_bbe.Race(r.comp, inputs.TRACK_LEN) for r in reqs]
+specs = [(race, None, 0, int(min(r.n_sims, 1000)), r.index, 1) for r, race in zip(reqs, races)]
+wins = torch.zeros((len(specs), 20), dtype=torch.int64, device="cuda")
+plan = _bbe.BatchPlan(specs, 5, wins, autotune=True)
+plan.launch()
+torch.cuda.synchronize()
+print(json.dumps(dict(plan.info(), wins=int(wins.sum().item()))))
+"""
+
+
+def test_tuning_cache_file_is_written_and_read(torch, tmp_path):
+    """A plan created with autotuning records its launch shape in the JSON
+    cache named by BBE_TUNE_CACHE; a fresh process creating a plan of the
+    same size class takes the shape from the file (an entry planted with a
+    distinctive shape is the one it uses), with the same results."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    cache = tmp_path / "tune.json"
+    env = dict(os.environ, BBE_TUNE_CACHE=str(cache))
+
+    def child():
+        out = subprocess.run([sys.executable, "-c", _TUNE_CHILD, root], env=env, timeout=180,
+                             capture_output=True, text=True, check=True).stdout
+        return json.loads(out.strip().splitlines()[-1])
+
+    announce("tuning cache: first process")
+    first = child()
+    text = cache.read_text()
+    data = json.loads(text)
+    assert len(data["entries"]) == 1
+    e = data["entries"][0]
+    assert {"device", "kernels", "size_class", "waves_per_block", "sims_per_item",
+            "cu_share"} <= set(e)
+    assert (e["waves_per_block"], e["sims_per_item"]) == \
+        (first["waves_per_block"], first["sims_per_item"])
+    # plant a shape the tuner would be unlikely to pick for this small batch
+    planted = dict(e, waves_per_block=1, sims_per_item=192, cu_share=2)
+    if (e["waves_per_block"], e["sims_per_item"]) == (1, 192):
+        planted["waves_per_block"] = 2
+    cache.write_text(json.dumps({"entries": [planted]}).replace("}]", "}\n]")
+                     .replace("[{", "[\n  {"))
+    announce("tuning cache: second process")
+    second = child()
+    assert (second["waves_per_block"], second["sims_per_item"]) == \
+        (planted["waves_per_block"], planted["sims_per_item"])
+    assert second["wins"] == first["wins"]
