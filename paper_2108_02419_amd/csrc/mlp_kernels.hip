@@ -43,40 +43,44 @@ __device__ __forceinline__ bf16x8 frag_glb(const uint16_t* __restrict__ W, int K
                                             8 * (lane >> 4));
 }
 
-// acc[rb][cb] = in[64 x K] (LDS) * W[n_base .. n_base + 16*NCB, 0 .. K)^T
-template <int K, int NCB>
+// acc[rb][cb] = in[16*RB x K] (LDS) * W[n_base .. n_base + 16*NCB, 0 .. K)^T.
+// The k blocks are accumulated in the same order for every row, so a row's
+// result does not depend on how many rows its workgroup holds.
+template <int RB, int K, int NCB>
 __device__ __forceinline__ void tile_gemm(const uint16_t* in, int S, const uint16_t* __restrict__ W,
-                                          int n_base, floatx4 (&acc)[4][NCB], int lane) {
+                                          int n_base, floatx4 (&acc)[RB][NCB], int lane) {
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
     for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 a[4], b[NCB];
+        bf16x8 a[RB], b[NCB];
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb) a[rb] = frag_lds(in, S, rb * 16, k0, lane);
+        for (int rb = 0; rb < RB; ++rb) a[rb] = frag_lds(in, S, rb * 16, k0, lane);
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) b[cb] = frag_glb(W, K, n_base + cb * 16, k0, lane);
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < NCB; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
     }
 }
 
-constexpr int kTile = 64;            // rows per workgroup
+// Rows per workgroup of the forward and backward-data kernels: 16 * RB,
+// RB = 1, 2 or 4, chosen per launch so that small batches still spread
+// over the chip.
 constexpr int kS = kHid + 8;         // LDS row stride of hidden tiles (bank spread)
 constexpr int kSin = kIn + 8;        // LDS row stride of the feature tile
 constexpr int kSout = kOutP + 8;     // LDS row stride of the dz tile
 
-// Copies rows [row0, row0 + 64) of a [B][K] bf16 matrix into an LDS tile
+// Copies rows [row0, row0 + R) of a [B][K] bf16 matrix into an LDS tile
 // (stride S), zero rows past B.  16-byte pieces.
-template <int K>
+template <int R, int K>
 __device__ __forceinline__ void load_tile(uint16_t* t, int S, const uint16_t* __restrict__ g,
                                           int row0, int B) {
     constexpr int P = K / 8;
-    for (int i = threadIdx.x; i < kTile * P; i += blockDim.x) {
+    for (int i = threadIdx.x; i < R * P; i += blockDim.x) {
         int r = i / P, c = (i - r * P) * 8;
         uint4 v = make_uint4(0, 0, 0, 0);
         if (row0 + r < B) v = *reinterpret_cast<const uint4*>(g + (size_t)(row0 + r) * K + c);
@@ -85,12 +89,12 @@ __device__ __forceinline__ void load_tile(uint16_t* t, int S, const uint16_t* __
 }
 
 // Hidden layer epilogue: bias, ReLU, bfloat16 into LDS (and global).
-template <int NCB>
-__device__ __forceinline__ void hidden_out(const floatx4 (&acc)[4][NCB], int n_base,
+template <int RB, int NCB>
+__device__ __forceinline__ void hidden_out(const floatx4 (&acc)[RB][NCB], int n_base,
                                            const float* __restrict__ bias, uint16_t* out, int S,
                                            uint16_t* __restrict__ g, int row0, int B, int lane) {
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < NCB; ++cb) {
             const int n = n_base + cb * 16 + (lane & 15);
@@ -105,41 +109,43 @@ __device__ __forceinline__ void hidden_out(const floatx4 (&acc)[4][NCB], int n_b
         }
 }
 
-// Forward pass of 64 rows; optional softmax cross-entropy epilogue.
+// Forward pass of 16 * RB rows; optional softmax cross-entropy epilogue.
+template <int RB>
 __global__ void __launch_bounds__(256) mlp_fwd_kernel(const MlpFwdArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t bufA[kTile * kS];
-    __shared__ __attribute__((aligned(16))) uint16_t bufB[kTile * kS];
-    __shared__ float logit[kTile][kOutP + 1];
+    constexpr int R = 16 * RB;
+    __shared__ __attribute__((aligned(16))) uint16_t bufA[R * kS];
+    __shared__ __attribute__((aligned(16))) uint16_t bufB[R * kS];
+    __shared__ float logit[R][kOutP + 1];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * kTile;
+    const int row0 = blockIdx.x * R;
 
-    load_tile<kIn>(bufA, kSin, a.x, row0, a.B);
+    load_tile<R, kIn>(bufA, kSin, a.x, row0, a.B);
     __syncthreads();
     {
-        floatx4 acc[4][4];
-        tile_gemm<kIn, 4>(bufA, kSin, a.w1, wave * 64, acc, lane);
-        hidden_out<4>(acc, wave * 64, a.b1, bufB, kS, a.h1, row0, a.B, lane);
+        floatx4 acc[RB][4];
+        tile_gemm<RB, kIn, 4>(bufA, kSin, a.w1, wave * 64, acc, lane);
+        hidden_out<RB, 4>(acc, wave * 64, a.b1, bufB, kS, a.h1, row0, a.B, lane);
     }
     __syncthreads();
     {
-        floatx4 acc[4][4];
-        tile_gemm<kHid, 4>(bufB, kS, a.w2, wave * 64, acc, lane);
-        hidden_out<4>(acc, wave * 64, a.b2, bufA, kS, a.h2, row0, a.B, lane);
+        floatx4 acc[RB][4];
+        tile_gemm<RB, kHid, 4>(bufB, kS, a.w2, wave * 64, acc, lane);
+        hidden_out<RB, 4>(acc, wave * 64, a.b2, bufA, kS, a.h2, row0, a.B, lane);
     }
     __syncthreads();
     {
-        floatx4 acc[4][4];
-        tile_gemm<kHid, 4>(bufA, kS, a.w3, wave * 64, acc, lane);
-        hidden_out<4>(acc, wave * 64, a.b3, bufB, kS, a.h3, row0, a.B, lane);
+        floatx4 acc[RB][4];
+        tile_gemm<RB, kHid, 4>(bufA, kS, a.w3, wave * 64, acc, lane);
+        hidden_out<RB, 4>(acc, wave * 64, a.b3, bufB, kS, a.h3, row0, a.B, lane);
     }
     __syncthreads();
     if (wave < 2) {  // 32 padded outputs: two column blocks, one per wave
-        floatx4 acc[4][1];
-        tile_gemm<kHid, 1>(bufB, kS, a.w4, wave * 16, acc, lane);
+        floatx4 acc[RB][1];
+        tile_gemm<RB, kHid, 1>(bufB, kS, a.w4, wave * 16, acc, lane);
         const int n = wave * 16 + (lane & 15);
         const float bn = n < kOut ? a.b4[n] : 0.0f;
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int i = 0; i < 4; ++i) logit[rb * 16 + 4 * (lane >> 4) + i][n] = acc[rb][0][i] + bn;
     }
@@ -147,7 +153,7 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(const MlpFwdArgs a) {
 
     // Masked softmax over the slots that hold a competitor, one row a thread.
     const int r = threadIdx.x;
-    if (r < kTile && row0 + r < a.B) {
+    if (r < R && row0 + r < a.B) {
         const size_t row = (size_t)(row0 + r);
         const int nv = min(max(a.n_valid[row], 1), kOut);  // 1..20 slots hold competitors
         float mx = -__builtin_inff();
@@ -184,11 +190,12 @@ __global__ void __launch_bounds__(256) mlp_fwd_kernel(const MlpFwdArgs a) {
 
 // Backward-data epilogue: gradient times ReLU mask of the forward
 // activation, bfloat16 into LDS (if given) and global.
-__device__ __forceinline__ void grad_out(const floatx4 (&acc)[4][4], int n_base,
+template <int RB>
+__device__ __forceinline__ void grad_out(const floatx4 (&acc)[RB][4], int n_base,
                                          const uint16_t* __restrict__ h, uint16_t* out, int S,
                                          uint16_t* __restrict__ g, int row0, int B, int lane) {
 #pragma unroll
-    for (int rb = 0; rb < 4; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             const int n = n_base + cb * 16 + (lane & 15);
@@ -204,30 +211,33 @@ __device__ __forceinline__ void grad_out(const floatx4 (&acc)[4][4], int n_base,
         }
 }
 
-// Gradients with respect to the three hidden layers' pre-activations.
+// Gradients with respect to the three hidden layers' pre-activations, for
+// 16 * RB rows.
+template <int RB>
 __global__ void __launch_bounds__(256) mlp_bwd_data_kernel(const MlpBwdArgs a) {
-    __shared__ __attribute__((aligned(16))) uint16_t bufA[kTile * kS];
-    __shared__ __attribute__((aligned(16))) uint16_t bufB[kTile * kS];
+    constexpr int R = 16 * RB;
+    __shared__ __attribute__((aligned(16))) uint16_t bufA[R * kS];
+    __shared__ __attribute__((aligned(16))) uint16_t bufB[R * kS];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int row0 = blockIdx.x * kTile;
-    load_tile<kOutP>(bufA, kSout, a.dz4, row0, a.B);
+    const int row0 = blockIdx.x * R;
+    load_tile<R, kOutP>(bufA, kSout, a.dz4, row0, a.B);
     __syncthreads();
     {
-        floatx4 acc[4][4];
-        tile_gemm<kOutP, 4>(bufA, kSout, a.w4t, wave * 64, acc, lane);
-        grad_out(acc, wave * 64, a.h3, bufB, kS, a.dz3, row0, a.B, lane);
+        floatx4 acc[RB][4];
+        tile_gemm<RB, kOutP, 4>(bufA, kSout, a.w4t, wave * 64, acc, lane);
+        grad_out<RB>(acc, wave * 64, a.h3, bufB, kS, a.dz3, row0, a.B, lane);
     }
     __syncthreads();
     {
-        floatx4 acc[4][4];
-        tile_gemm<kHid, 4>(bufB, kS, a.w3t, wave * 64, acc, lane);
-        grad_out(acc, wave * 64, a.h2, bufA, kS, a.dz2, row0, a.B, lane);
+        floatx4 acc[RB][4];
+        tile_gemm<RB, kHid, 4>(bufB, kS, a.w3t, wave * 64, acc, lane);
+        grad_out<RB>(acc, wave * 64, a.h2, bufA, kS, a.dz2, row0, a.B, lane);
     }
     __syncthreads();
     {
-        floatx4 acc[4][4];
-        tile_gemm<kHid, 4>(bufA, kS, a.w2t, wave * 64, acc, lane);
-        grad_out(acc, wave * 64, a.h1, nullptr, kS, a.dz1, row0, a.B, lane);
+        floatx4 acc[RB][4];
+        tile_gemm<RB, kHid, 4>(bufA, kS, a.w2t, wave * 64, acc, lane);
+        grad_out<RB>(acc, wave * 64, a.h1, nullptr, kS, a.dz1, row0, a.B, lane);
     }
 }
 
@@ -447,12 +457,27 @@ __global__ void fill_f32_kernel(float* __restrict__ p, float v, int n) {
 
 // ---------------------------------------------------------------- launchers
 
+// Row blocks per workgroup for a batch: the most (up to 4) that still give
+// at least 256 workgroups, else 1.
+static int row_blocks(int B) {
+    if ((B + 63) / 64 >= 256) return 4;
+    if ((B + 31) / 32 >= 256) return 2;
+    return 1;
+}
 hipError_t launch_mlp_fwd(const MlpFwdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_fwd_kernel, dim3((a.B + kTile - 1) / kTile), dim3(256), 0, s, a);
+    switch (row_blocks(a.B)) {
+        case 4: hipLaunchKernelGGL(mlp_fwd_kernel<4>, dim3((a.B + 63) / 64), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(mlp_fwd_kernel<2>, dim3((a.B + 31) / 32), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(mlp_fwd_kernel<1>, dim3((a.B + 15) / 16), dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 hipError_t launch_mlp_bwd_data(const MlpBwdArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(mlp_bwd_data_kernel, dim3((a.B + kTile - 1) / kTile), dim3(256), 0, s, a);
+    switch (row_blocks(a.B)) {
+        case 4: hipLaunchKernelGGL(mlp_bwd_data_kernel<4>, dim3((a.B + 63) / 64), dim3(256), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(mlp_bwd_data_kernel<2>, dim3((a.B + 31) / 32), dim3(256), 0, s, a); break;
+        default: hipLaunchKernelGGL(mlp_bwd_data_kernel<1>, dim3((a.B + 15) / 16), dim3(256), 0, s, a); break;
+    }
     return hipGetLastError();
 }
 hipError_t launch_mlp_wgrad(const MlpWgradArgs& a, int n_tiles, hipStream_t s) {

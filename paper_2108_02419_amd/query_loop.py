@@ -51,6 +51,19 @@ def _probs_from_wins(wins, n):
     return w / tot if tot > 0 else np.full(n, 1.0 / n)
 
 
+STRICT_Z = 6.0  # standard errors of a strict fallback answer that fit inside the error bound
+
+
+def strict_sims(pooled, bound=0.02, z=STRICT_Z, lo=1024, hi=1 << 20):
+    """Simulations per bettor for a fallback answer whose noise keeps it
+    within `bound` of the truth: the largest binomial variance p(1 - p) of
+    the round's pooled audit estimate, times (z / bound)^2, rounded up to
+    whole 64-simulation generations."""
+    v = float(np.max(pooled * (1.0 - pooled))) if len(pooled) else 0.25
+    n = int(math.ceil(v * (z / bound) ** 2 / 64.0)) * 64
+    return int(min(max(n, lo), hi))
+
+
 def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
         fallback_sims=25_000, judge_sims=1_000_000, gate=None, audit_tol=0.0175,
         baseline_every=10, max_rounds=None, log=print, on_round=None):
@@ -63,7 +76,12 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
     unless its entropy exceeds `gate` (default 0.95 ln n) or it differs from
     the audit's pooled estimate (all audited simulations together) by more
     than `audit_tol` for some competitor; otherwise every bettor is answered
-    by Monte-Carlo at `fallback_sims` simulations.  A Monte-Carlo judge at
+    by Monte-Carlo at `fallback_sims` simulations: a number, "strict"
+    (sized each round by strict_sims from the audit's pooled estimate), or
+    a list of these -- every entry runs and is timed in the same rounds,
+    the first one gives the answers reported as the system's and passed to
+    `on_round`; the results hold each entry's rates and errors under
+    `fallbacks`.  A Monte-Carlo judge at
     `judge_sims` measures the error of every answer.  Every
     `baseline_every`-th round also times the plain Monte-Carlo path (every
     bettor at `mc_sims`): the rate the system is compared with.
@@ -104,6 +122,10 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / 1e3
 
+    fb_specs = list(fallback_sims) if isinstance(fallback_sims, (list, tuple)) else [fallback_sims]
+    fb_time = [0.0] * len(fb_specs)
+    fb_errs = [[] for _ in fb_specs]
+    fb_sims = [[] for _ in fb_specs]
     state = None
     rounds = []
     sur_s = audit_s = fb_s = base_s = 0.0
@@ -150,14 +172,21 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
 
         fb_c = None
         t_fb = 0.0
-        if flagged:  # every bettor: its own Monte-Carlo at the fallback size
+        fb_round = []
+        if flagged:  # every bettor: its own Monte-Carlo at each fallback size
             fbase = (0x20000000 + k * n_bettors) & 0x3FFFFFFF
-            fplan, fprobs, _ = _mc_answers(race, state, n, n_bettors,
-                                           fbase + np.arange(n_bettors), fallback_sims, seed + 3)
-            t_fb = timed(fplan.launch)
+            for j, spec in enumerate(fb_specs):
+                sims = strict_sims(pooled) if spec == "strict" else int(spec)
+                fplan, fprobs, _ = _mc_answers(race, state, n, n_bettors,
+                                               fbase + np.arange(n_bettors), sims, seed + 3)
+                t = timed(fplan.launch)
+                fplan.free()
+                ans_j = fprobs.cpu().numpy()[:, :n]
+                fb_round.append((sims, t, ans_j))
+                fb_time[j] += t
+                if j == 0:
+                    t_fb, fb_c = t, ans_j
             fb_s += t_fb
-            fplan.free()
-            fb_c = fprobs.cpu().numpy()[:, :n]
 
         t_base = None
         if baseline_every and k % baseline_every == 0:  # the plain Monte-Carlo path
@@ -178,6 +207,9 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
         sur_err = float(np.abs(sur_c - judge).max())
         mc_err = float(np.abs(mc_c - judge[None, :]).max())
         fb_err = float(np.abs(fb_c - judge[None, :]).max()) if flagged else None
+        for j, (sims, t, ans_j) in enumerate(fb_round):
+            fb_errs[j].append(float(np.abs(ans_j - judge[None, :]).max()))
+            fb_sims[j].append(sims)
         if on_round is not None:
             on_round(dict(round=k, state=state, ask=ask, requests=base + ask,
                           mc_seed=seed + 1, judge_request=0x40000000 | k,
@@ -212,8 +244,20 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
             return None
         return dict(max=float(a.max()), mean=float(a.mean()),
                     p99=float(np.quantile(a, 0.99)), p999=float(np.quantile(a, 0.999)))
+    served_errs = np.array([r["sur_err"] for r in rounds if not r["flagged"]])
+    variants = []
+    for j, spec in enumerate(fb_specs):
+        t_sys = sur_s + audit_s + fb_time[j]
+        all_err = np.concatenate([served_errs, np.asarray(fb_errs[j], np.float64)])
+        variants.append(dict(fallback_sims=spec,
+                             mean_sims=float(np.mean(fb_sims[j])) if fb_sims[j] else None,
+                             fallback_seconds=fb_time[j],
+                             system_queries_per_s=total_q / t_sys,
+                             system_speedup=(total_q / t_sys) / mc_qps,
+                             fallback_err=stats(fb_errs[j]), answer_err=stats(all_err)))
     return dict(rounds=len(rounds), bettors=n_bettors, every=every, mc_sims=mc_sims,
-                fallback_sims=fallback_sims, judge_sims=judge_sims, entropy_threshold=thr,
+                fallback_sims=fb_specs[0], fallbacks=variants, judge_sims=judge_sims,
+                entropy_threshold=thr,
                 audit_frac=audit_frac, audit_tol=audit_tol,
                 surrogate_queries_per_s=total_q / sur_s, mc_queries_per_s=mc_qps,
                 speedup=(total_q / sur_s) / mc_qps,
@@ -232,7 +276,8 @@ def main():
                     help="trained surrogate: a saved network (bbe_mlp_save) or parameters (.npy)")
     ap.add_argument("--every", type=int, default=1)
     ap.add_argument("--bettors", type=int, default=10_000)
-    ap.add_argument("--fallback-sims", type=int, default=25_000)
+    ap.add_argument("--fallback-sims", nargs="+", default=["25000"],
+                    help="fallback simulations per bettor: numbers and/or 'strict'")
     ap.add_argument("--judge-sims", type=int, default=1_000_000)
     ap.add_argument("--audit-tol", type=float, default=0.0175)
     ap.add_argument("--max-rounds", type=int, default=None)
@@ -247,7 +292,8 @@ def main():
     else:
         net = _bbe.Mlp.load(args.params, max_batch=8)
     t0 = time.perf_counter()
-    res = run(net, every=args.every, n_bettors=args.bettors, fallback_sims=args.fallback_sims,
+    fbs = [f if f == "strict" else int(f) for f in args.fallback_sims]
+    res = run(net, every=args.every, n_bettors=args.bettors, fallback_sims=fbs,
               judge_sims=args.judge_sims, gate=args.gate, audit_tol=args.audit_tol,
               max_rounds=args.max_rounds, log=lambda m: print(f"[query] {m}", flush=True))
     res["wall_s"] = time.perf_counter() - t0

@@ -155,9 +155,10 @@ def test_query_loop_end_to_end(torch, orc, gate):
     params = inputs.surrogate_random(8)
     rounds = []
     announce(f"query loop gate={gate}")
-    res = query_loop.run(params, every=7, n_bettors=300, mc_sims=400, fallback_sims=300,
-                         judge_sims=3000, gate=gate, audit_tol=1.0, baseline_every=2,
-                         max_rounds=3, log=lambda m: None, on_round=rounds.append)
+    res = query_loop.run(params, every=7, n_bettors=300, mc_sims=400,
+                         fallback_sims=[300, "strict"], judge_sims=3000, gate=gate,
+                         audit_tol=1.0, baseline_every=2, max_rounds=3, log=lambda m: None,
+                         on_round=rounds.append)
     assert res["rounds"] == 3 and len(rounds) == 3
     assert res["flagged_rounds"] == (3 if gate < 0 else 0)
     trace = orc.race_trace(comp, L, seed, real, 0, 40)
@@ -217,3 +218,13 @@ def test_query_loop_end_to_end(torch, orc, gate):
         else:
             assert pr["answer_err"] == pr["sur_err"]
     assert res["seconds"]["baseline_rounds"] == 2  # rounds 0 and 2
+    # both fallback sizes ran in the flagged rounds; the strict one is sized
+    # from each round's pooled audit estimate
+    first, strict = res["fallbacks"]
+    assert first["fallback_sims"] == 300 and strict["fallback_sims"] == "strict"
+    if gate < 0:
+        want = np.mean([query_loop.strict_sims(rd["pooled"]) for rd in rounds])
+        assert first["mean_sims"] == 300 and strict["mean_sims"] == want
+        assert first["answer_err"]["max"] == res["answer_err"]["max"]
+    else:
+        assert first["mean_sims"] is None and strict["fallback_seconds"] == 0.0

@@ -95,6 +95,58 @@ def test_forward_layer_by_layer_with_biases(torch):
         np.testing.assert_allclose(pg, q, atol=2e-3)
 
 
+def _check_rows(H, zg, params, X, n, sel):
+    """The per-layer check of _check_layers on rows `sel` of a batch whose
+    hidden activations H [3, B, 256] and logits zg [B, 20] the GPU returned."""
+    P = ref.unpack(np.asarray(params, np.float32).astype(np.float64))
+    inp = ref.bf16(X[sel])
+    for k in range(3):
+        a, e = ref.dense_with_bound(inp, P[f"W{k + 1}"], P[f"b{k + 1}"])
+        lo, hi = ref.bf16_interval(a, e, relu=True)
+        h = H[k][sel]
+        assert not ((h < lo) | (h > hi)).any(), k + 1
+        inp = h
+    z, e = ref.dense_with_bound(inp, P["W4"], P["b4"])
+    mask = np.arange(20)[None, :] < n[sel][:, None]
+    assert (np.abs(zg[sel] - z) <= e)[mask].all()
+
+
+def test_row_tiles_of_every_size_give_the_same_rows(torch):
+    """Batches large enough for 32- and 64-row workgroups (8200 and 16400
+    rows, both ragged) pass the per-layer check on their first and last
+    rows, and a row's logits are the same bits whichever tile size its
+    batch gets (16 rows at 200)."""
+    rng = np.random.default_rng(9)
+    params = inputs.surrogate_random(3)
+    net = _bbe.Mlp(params, max_batch=8)
+    X, n, _ = _features(rng, 16400)
+    outs = {}
+    for B in (200, 8200, 16400):
+        announce(f"mlp forward row tiles B={B}")
+        xt, nt = _bits(torch, X[:B]), torch.tensor(n[:B], device="cuda")
+        hidden = torch.empty((3, B, 256), dtype=torch.int16, device="cuda")
+        logits = torch.empty((B, 32), dtype=torch.float32, device="cuda")
+        net.forward_hidden(xt, nt, hidden, logits)
+        torch.cuda.synchronize()
+        zg = logits.cpu().numpy()[:, :20].astype(np.float64)
+        outs[B] = zg
+        sel = np.r_[0:min(B, 300), max(0, B - 300):B]  # the first tiles and the ragged tail
+        _check_rows(_bf16_of_bits(hidden), zg, params, X[:B], n[:B], sel)
+    np.testing.assert_array_equal(outs[8200][:200], outs[200])
+    np.testing.assert_array_equal(outs[16400][:8200], outs[8200])
+
+
+def test_gradients_with_large_row_tiles(torch):
+    """The backward-data kernel at 64-row tiles (16400 rows) against the
+    reference."""
+    rng = np.random.default_rng(10)
+    params = inputs.surrogate_random(2)
+    X, n, T = _features(rng, 16400)
+    net = _bbe.Mlp(params, max_batch=16400)
+    announce("mlp gradients B=16400")
+    _grad_check(torch, net, params, X, n, T)
+
+
 def test_forward_layer_by_layer_after_adam_steps(torch):
     """After training steps the kernels use the refreshed bfloat16 copies of
     the updated master parameters, biases included."""

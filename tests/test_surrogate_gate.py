@@ -41,3 +41,18 @@ def test_gated_errors_mix_surrogate_and_monte_carlo_answers():
     pred2 = pred.copy(); pred2[:, 5] = 0.9
     assert abs(S.gated_errors(_t(pred2), _t(ent), _t(mc), _t(ref), _t(n), 0.5)
                ["served_max_err"] - 0.01) < 1e-12
+
+
+def test_strict_fallback_size_follows_the_largest_binomial_variance():
+    """A strict fallback answer's standard error stays 6 times inside the
+    0.02 bound: sims = max p(1-p) * (6 / 0.02)^2, whole generations of 64,
+    clamped to [1024, 2^20]."""
+    from paper_2108_02419_amd import query_loop as Q
+    assert Q.strict_sims(np.array([0.5, 0.5])) == 22528          # 22500 -> 352 * 64
+    assert Q.strict_sims(np.array([0.9, 0.05, 0.05])) == 8128     # 0.09 * 90000 = 8100
+    assert Q.strict_sims(np.array([1.0, 0.0])) == 1024            # decided race: the floor
+    for p in (np.array([0.3, 0.7]), np.array([0.62, 0.2, 0.18])):
+        n = Q.strict_sims(p)
+        assert n % 64 == 0
+        se = np.sqrt(np.max(p * (1 - p)) / n)
+        assert 6 * se <= 0.02 < 6 * np.sqrt(np.max(p * (1 - p)) / (n - 64))
