@@ -115,8 +115,9 @@ class BlockStates:
     races, in-play states produced by the model's own runs, and the request
     table of their Monte-Carlo answers."""
 
-    def __init__(self, block: int, seed: int, count: int = inputs.SURROGATE_BLOCK):
-        a = inputs.surrogate_state_block(block, count)
+    def __init__(self, block: int, seed: int, count: int = inputs.SURROGATE_BLOCK,
+                 cfg: dict = inputs.CFG_SURROGATE):
+        a = inputs.surrogate_state_block(block, count, cfg)
         self.block, self.count = block, count
         self.n = a["n"]
         self.comp = a["comp"]
@@ -160,7 +161,8 @@ class BlockStates:
                            probs, target)
 
 
-def build_training_set(n_states: int, label_sims: int, seed: int, log=None):
+def build_training_set(n_states: int, label_sims: int, seed: int, log=None, block0: int = 0,
+                       cfg: dict = inputs.CFG_SURROGATE):
     """n_states training states (blocks 0, 1, ... of the state recipe) with
     Monte-Carlo labels of label_sims simulations each (winner only), kept on
     the GPU only: features x int16 [B, 160], n int32 [B], targets float32
@@ -174,7 +176,7 @@ def build_training_set(n_states: int, label_sims: int, seed: int, log=None):
     t0 = time.perf_counter()
     for b, lo in enumerate(range(0, n_states, inputs.SURROGATE_BLOCK)):
         cnt = min(inputs.SURROGATE_BLOCK, n_states - lo)
-        st = BlockStates(b, seed, cnt)
+        st = BlockStates(block0 + b, seed, cnt, cfg)
         t1 = time.perf_counter()
         probs, steps = st.mc(label_sims, seed, request_base=lo)
         mc_s += time.perf_counter() - t1
@@ -287,7 +289,7 @@ EVAL_BLOCK0 = 4096  # held-out states come from blocks 4096, 4097, ... (training
 
 
 def build_eval_set(n_states: int, judge_sims: int, seed: int, fallback_sims=(10_000,),
-                   rp_sims=(), block0: int = EVAL_BLOCK0):
+                   rp_sims=(), block0: int = EVAL_BLOCK0, cfg: dict = inputs.CFG_SURROGATE):
     """Held-out states with a high-sample Monte-Carlo judge and, for each
     entry of fallback_sims and rp_sims, Monte-Carlo answers of that many
     simulations (the fallback's and RP(d) bettors' own answers).  Device
@@ -297,7 +299,7 @@ def build_eval_set(n_states: int, judge_sims: int, seed: int, fallback_sims=(10_
     ans = {d: [] for d in tuple(fallback_sims) + tuple(rp_sims)}
     for b, lo in enumerate(range(0, n_states, inputs.SURROGATE_BLOCK)):
         cnt = min(inputs.SURROGATE_BLOCK, n_states - lo)
-        st = BlockStates(block0 + b, seed, cnt)
+        st = BlockStates(block0 + b, seed, cnt, cfg)
         x = torch.empty((cnt, 160), dtype=torch.int16, device=dev)
         jt = torch.empty((cnt, 20), dtype=torch.float32, device=dev)
         jp, _ = st.mc(judge_sims, seed + 1, request_base=(1 << 24) + lo)

@@ -268,3 +268,32 @@ def test_tuning_cache_file_is_written_and_read(torch, tmp_path):
     assert (second["waves_per_block"], second["sims_per_item"]) == \
         (planted["waves_per_block"], planted["sims_per_item"])
     assert second["wins"] == first["wins"]
+
+
+def test_work_list_cap_lengthens_items(torch, orc):
+    """A batch of more than 2^20 generations (two requests of 3.5*10^7
+    simulations) is cut into fewer, longer work items; its win counts and
+    competitor-steps equal those of bbe_race_sim on each request, bit for
+    bit."""
+    reqs = inputs.batch_requests(n_requests=40)
+    small = [r for r in reqs if r.n <= 6][:2]
+    assert len(small) == 2
+    races = [Race(r.comp, L) for r in small]
+    # late in the race: short simulations
+    states = [orc.race_prefix(r.comp, L, SEED, r.prefix_request, 0, np.float32(1900.0))
+              for r in small]
+    n_sims = 35_000_000
+    specs = [(race, st, 0, n_sims, r.index, 1) for r, st, race in zip(small, states, races)]
+    announce("work-list cap: 2 x 3.5e7 sims")
+    plan, wins, probs, steps = _run_plan(torch, specs, SEED, autotune=False)
+    info = plan.info()
+    assert info["sims_per_item"] > 64 and info["n_items"] <= (1 << 20)
+    total = 0
+    for i, (race, st, _, n, req, stop) in enumerate(specs):
+        w = torch.zeros(race.n, dtype=torch.int64, device="cuda")
+        s = torch.zeros(1, dtype=torch.int64, device="cuda")
+        _bbe.race_sim(race, n, SEED, request=req, state=st, stop_after=stop, wins=w, steps=s)
+        torch.cuda.synchronize()
+        assert torch.equal(wins[i, :race.n], w), i
+        total += int(s.item())
+    assert int(steps.item()) == total
