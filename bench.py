@@ -643,10 +643,11 @@ def gated_leg(eval_states: int = 1000, judge_sims: int = 1_000_000, audit_tol: f
     surrogate serves a round when its entropy is below 0.95 ln n and it
     agrees with the pooled 1% audit (10^4 simulations per audited bettor)
     within audit_tol, else every bettor gets its own Monte-Carlo answer --
-    at the plain path's 10^4 simulations (the design's fallback), and, timed
-    on the same rounds, at the strict size that keeps every answer within
-    0.02 of the truth (query_loop.strict_sims); the plain Monte-Carlo path
-    (every bettor at 10^4 simulations) is timed on every 10th round."""
+    at the strict size that keeps every answer within 0.02 of the truth
+    (query_loop.strict_sims; the headline figures), and, timed on the same
+    rounds, at the plain path's 10^4 simulations (`fallback_1e4`); the plain
+    Monte-Carlo path (every bettor at 10^4 simulations) is timed on every
+    10th round."""
     import torch
 
     from paper_2108_02419_amd import _bbe, query_loop, surrogate
@@ -669,27 +670,31 @@ def gated_leg(eval_states: int = 1000, judge_sims: int = 1_000_000, audit_tol: f
                           audit_tol=audit_tol, log=lambda m: print(f"[query] {m}", flush=True))
     loop_s = time.perf_counter() - t1
     plain, strict = loop["fallbacks"]
+    # the headline figures are those of the strict fallback: the system
+    # whose every answer is held to the 0.02 target; the 10^4-simulation
+    # fallback (the Monte-Carlo path's own answers) is reported beside it
     return {"workload": f"query race n=20, {loop['rounds']} rounds x {loop['bettors']} bettors; "
                         f"surrogate from {os.path.relpath(TRAINED, ROOT)}; audit 1% at "
                         f"{loop['mc_sims']} sims, pooled, tolerance {audit_tol}; fallback "
-                        f"per bettor at 10^4 sims (the Monte-Carlo path's own answers) and, "
-                        f"on the same rounds, at the strict size; judge {judge_sims} sims",
-            "strict": {"note": "every answer within 0.02 of the judge: fallback sized per "
-                               "round from the audit's pooled estimate",
-                       "system_queries_per_s": strict["system_queries_per_s"],
-                       "system_speedup": strict["system_speedup"],
-                       "answer_err_max": strict["answer_err"]["max"],
-                       "answer_err": strict["answer_err"],
-                       "fallback_mean_sims": strict["mean_sims"],
-                       "fallback_err": strict["fallback_err"]},
-            "system_queries_per_s": plain["system_queries_per_s"],
+                        f"per bettor at the strict size (every answer within 0.02) and, on the "
+                        f"same rounds, at 10^4 sims; judge {judge_sims} sims",
+            "system_queries_per_s": strict["system_queries_per_s"],
             "mc_queries_per_s": loop["mc_queries_per_s"],
-            "system_speedup": plain["system_speedup"],
-            "answer_err_max": plain["answer_err"]["max"],
-            "answer_err": plain["answer_err"],
+            "system_speedup": strict["system_speedup"],
+            "answer_err_max": strict["answer_err"]["max"],
+            "answer_err": strict["answer_err"],
+            "fallback_mean_sims": strict["mean_sims"],
+            "fallback_err": strict["fallback_err"],
+            "fallback_1e4": {"note": "the same rounds with every flagged bettor answered at "
+                                     "10^4 simulations, the Monte-Carlo path's own answers "
+                                     "(their noise exceeds 0.02 on some states)",
+                             "system_queries_per_s": plain["system_queries_per_s"],
+                             "system_speedup": plain["system_speedup"],
+                             "answer_err_max": plain["answer_err"]["max"],
+                             "answer_err": plain["answer_err"],
+                             "fallback_err": plain["fallback_err"]},
             "served_frac": loop["served_frac"],
             "served_err": loop["served_err"],
-            "fallback_err": plain["fallback_err"],
             "audit_mc_err": loop["mc_err"],
             "surrogate_raw_speedup": loop["speedup"],
             "surrogate_raw_err": loop["surrogate_err"],
