@@ -39,7 +39,20 @@ KIND_NAMES = ("ZI", "LW", "UD", "LinEx")
 
 
 def run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=None, judge_every=0,
-        judge_sims=1_000_000, n_cheap=0, report_every=25, log=print):
+        judge_sims=1_000_000, n_cheap=0, report_every=25, log=print, on_round=None):
+    """Steps the query race `every` ticks at a time until its first
+    finisher; each round, every RP(d) bettor runs its d dry-runs (winner
+    only, its own request id = its index, plan seed = race seed + 3) from
+    the state reached, and takes the competitor that won most of them as
+    its view; `n_cheap` cheap bettors re-form their views from the race's
+    trace at the same tick.  `judge_every` > 0 measures the RP(d)
+    estimates' error against a `judge_sims` Monte-Carlo run every that
+    many rounds.
+
+    `on_round`, when given, receives each round's host copies: the state
+    (tick, pos, prev), the bettors' d, the plan seed, their win counts and
+    probabilities ([bettors, 20]), the RP views and view counts and, with
+    cheap bettors, the trace row and their views and view counts."""
     cfg = inputs.CFG_QUERY
     q = inputs.query_race(cfg)
     comp, seed, real_req = q["comp"], q["seed"], q["real_request"]
@@ -119,6 +132,15 @@ def run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=None, judge_ever
             backing[int(state[0])] = frac
         csteps += int(steps.item())
         dry_runs += int(d.sum())
+        if on_round is not None:
+            rd = dict(round=rounds, state=state, d=d, plan_seed=seed + 3,
+                      wins=wins.cpu().numpy(), probs=probs.cpu().numpy(),
+                      rp_views=rp_views.cpu().numpy(), rp_counts=rp_counts.cpu().numpy(),
+                      steps=int(steps.item()))
+            if cheap is not None and row < n_rows:
+                rd.update(row=row, cheap_views=cheap_views[0].cpu().numpy(),
+                          cheap_counts=cheap_counts[0].cpu().numpy())
+            on_round(rd)
         rounds += 1
         if judge_every and rounds % judge_every == 0:
             judged.append(_judge(race, state, n, probs, d, judge_sims, seed, rounds))

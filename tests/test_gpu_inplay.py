@@ -11,13 +11,17 @@ bettors re-estimating while one real race runs):
 - the query loop end to end on a few rounds: the watched race's states,
   sampled Monte-Carlo answers and the judge bit for bit against the oracle,
   the encoded features bit for bit, the surrogate's answers against the
-  float64 reference network."""
+  float64 reference network;
+- the RP(d) bettor loop end to end on a few rounds: every bettor's win
+  counts and probabilities from its own dry-runs, the RP views and the
+  cheap bettors' views bit for bit against the oracle."""
 import numpy as np
 import pytest
 
 from gpu_util import announce, require_gpu
+from oracle import bettors as OB
 from oracle import mlp as ref
-from paper_2108_02419_amd import _bbe, inputs, query_loop
+from paper_2108_02419_amd import _bbe, bettors, inputs, query_loop
 from paper_2108_02419_amd._bbe import BatchPlan, Race
 
 pytestmark = pytest.mark.gpu
@@ -228,3 +232,55 @@ def test_query_loop_end_to_end(torch, orc, gate):
         assert first["answer_err"]["max"] == res["answer_err"]["max"]
     else:
         assert first["mean_sims"] is None and strict["fallback_seconds"] == 0.0
+
+
+def test_rp_bettor_loop_end_to_end(torch, orc):
+    """Three rounds, 6 ticks apart, 48 RP(d) bettors (d log-uniform in
+    1..40) and 256 cheap bettors: each round's state against the oracle's
+    trace of the race; every bettor's win counts (its d dry-runs, request =
+    its index, from that state, winner only) and probabilities, the RP
+    views and their counts, and the cheap bettors' views at the same tick,
+    all bit for bit; the loop's dry-run and competitor-step totals are the
+    oracle's."""
+    q = inputs.query_race()
+    comp, seed, real = q["comp"], q["seed"], q["real_request"]
+    n = comp.shape[0]
+    rounds = []
+    announce("RP(d) bettor loop")
+    res = bettors.run(n_bettors=48, d_lo=1, d_hi=40, every=6, max_rounds=3, n_cheap=256,
+                      report_every=0, log=lambda m: None, on_round=rounds.append)
+    assert res["rounds"] == 3 and len(rounds) == 3
+    trace = orc.race_trace(comp, L, seed, real, 0, 40)
+    kinds, params = inputs.cheap_bettors(n_bettors=256)
+    d = rounds[0]["d"]
+    assert d.min() >= 1 and d.max() <= 40
+    total_steps = 0
+    for k, rd in enumerate(rounds):
+        tick, pos, prev = rd["state"]
+        want = _oracle_state_at(orc, comp, seed, real, 6 * (k + 1), trace)
+        assert tick == want[0] == 6 * (k + 1)
+        np.testing.assert_array_equal(pos, want[1])
+        np.testing.assert_array_equal(prev, want[2])
+        W = np.zeros((48, n), np.uint64)
+        steps = 0
+        for i in range(48):
+            _, w, s = orc.race_sim(comp, L, int(d[i]), rd["plan_seed"], request=i,
+                                   state=rd["state"], stop_after=1, want_orders=False, threads=8)
+            W[i] = w
+            steps += s
+            np.testing.assert_array_equal(rd["wins"][i, :n].astype(np.uint64), w,
+                                          err_msg=f"round {k} bettor {i}")
+            np.testing.assert_array_equal(rd["probs"][i, :n], orc.win_probs(w))
+        assert (rd["wins"][:, n:] == 0).all()
+        assert rd["steps"] == steps
+        total_steps += steps
+        v, c = OB.rp_views(W, n)
+        np.testing.assert_array_equal(rd["rp_views"], v)
+        np.testing.assert_array_equal(rd["rp_counts"].astype(np.uint32), c)
+        assert rd["row"] == tick
+        cv, cc = OB.views(kinds, params, trace, L, 0, inputs.CFG_VIEWS["views_seed"],
+                          rd["row"], 1)
+        np.testing.assert_array_equal(rd["cheap_views"], cv[0])
+        np.testing.assert_array_equal(rd["cheap_counts"].astype(np.uint32), cc[0])
+    assert res["dry_runs"] == 3 * int(d.sum())
+    assert res["competitor_steps"] == total_steps
