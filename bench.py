@@ -23,7 +23,9 @@ workloads of the path: `cfg0` (5 competitors, 10^3 simulations), `batch`
 Monte-Carlo at 10^4 simulations per query, on the same in-play state),
 `bettors` (10^4 RP(d) bettors re-running their dry-runs every tick of an
 in-play race) and `surrogate_gated` (the trained network, gated to the 0.02
-error target by the pooled 1% audit, over a whole in-play query loop).
+error target by the pooled 1% audit, over a whole in-play query loop; the
+same for races of 0.1-second ticks queried every 10 ticks in
+`surrogate_gated_dt01`).
 """
 from __future__ import annotations
 
@@ -319,6 +321,10 @@ def main() -> int:
         line["views"] = views_leg()
     if not args.no_gated:
         line["surrogate_gated"] = gated_leg()
+        # the query loop as first specified: 0.1-second ticks, a round every
+        # 10 ticks (the plain path timed on every 30th round)
+        line["surrogate_gated_dt01"] = gated_leg(trained=TRAINED_DT01, dt=0.1, every=10,
+                                                 baseline_every=30)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(c)
         line["cpu_baselines_other"] = cpu_baselines(line["cpu_baseline"]["cores"])
@@ -632,9 +638,11 @@ def views_leg(steps: int = 20):
 
 
 TRAINED = os.path.join(ROOT, "paper_2108_02419_amd", "trained", "surrogate.bbemlp")
+TRAINED_DT01 = os.path.join(ROOT, "paper_2108_02419_amd", "trained", "surrogate_dt01.bbemlp")
 
 
-def gated_leg(eval_states: int = 1000, judge_sims: int = 1_000_000, audit_tol: float = 0.0175):
+def gated_leg(eval_states: int = 1000, judge_sims: int = 1_000_000, audit_tol: float = 0.0175,
+              trained: str = TRAINED, dt: float = 1.0, every: int = 1, baseline_every: int = 10):
     """Surrogate vs Monte-Carlo queries per second at the error target, with
     the network trained by paper_2108_02419_amd.surrogate (its file and
     recipe in paper_2108_02419_amd/trained/): first judged afresh on held-out
@@ -647,18 +655,21 @@ def gated_leg(eval_states: int = 1000, judge_sims: int = 1_000_000, audit_tol: f
     (query_loop.strict_sims; the headline figures), and, timed on the same
     rounds, at the plain path's 10^4 simulations (`fallback_1e4`); the plain
     Monte-Carlo path (every bettor at 10^4 simulations) is timed on every
-    10th round."""
+    `baseline_every`-th round.  `dt` (seconds per tick) and `every` (ticks
+    per round) select the race's time step; `trained` is the network trained
+    at that step."""
     import torch
 
-    from paper_2108_02419_amd import _bbe, query_loop, surrogate
-    if not os.path.exists(TRAINED):
-        return {"skipped": f"{TRAINED} missing"}
-    net = _bbe.Mlp.load(TRAINED, max_batch=8)
+    from paper_2108_02419_amd import _bbe, inputs, query_loop, surrogate
+    if not os.path.exists(trained):
+        return {"skipped": f"{trained} missing"}
+    net = _bbe.Mlp.load(trained, max_batch=8)
     t0 = time.perf_counter()
     # held-out states from blocks the training never used
     ex, en, jt, ans = surrogate.build_eval_set(eval_states, judge_sims, 4,
                                                fallback_sims=(10_000,),
-                                               block0=surrogate.EVAL_BLOCK0 + 64)
+                                               block0=surrogate.EVAL_BLOCK0 + 64,
+                                               cfg=dict(inputs.CFG_SURROGATE, dt=dt))
     pred, ent = surrogate.predict(net, ex, en)
     torch.cuda.synchronize()
     heldout = {"states": eval_states, "judge_sims": judge_sims,
@@ -666,15 +677,19 @@ def gated_leg(eval_states: int = 1000, judge_sims: int = 1_000_000, audit_tol: f
                "mc_1e4": surrogate.errors(ans[10_000], jt, en)}
     judge_s = time.perf_counter() - t0
     t1 = time.perf_counter()
-    loop = query_loop.run(net, judge_sims=judge_sims, fallback_sims=[10_000, "strict"],
-                          audit_tol=audit_tol, log=lambda m: print(f"[query] {m}", flush=True))
+    loop = query_loop.run(net, every=every, judge_sims=judge_sims,
+                          fallback_sims=[10_000, "strict"], audit_tol=audit_tol,
+                          baseline_every=baseline_every,
+                          log=lambda m: print(f"[query] {m}", flush=True),
+                          cfg=dict(inputs.CFG_QUERY, dt=dt))
     loop_s = time.perf_counter() - t1
     plain, strict = loop["fallbacks"]
     # the headline figures are those of the strict fallback: the system
     # whose every answer is held to the 0.02 target; the 10^4-simulation
     # fallback (the Monte-Carlo path's own answers) is reported beside it
-    return {"workload": f"query race n=20, {loop['rounds']} rounds x {loop['bettors']} bettors; "
-                        f"surrogate from {os.path.relpath(TRAINED, ROOT)}; audit 1% at "
+    return {"workload": f"query race n=20, dt {dt} s, {loop['rounds']} rounds (every {every} "
+                        f"ticks) x {loop['bettors']} bettors; "
+                        f"surrogate from {os.path.relpath(trained, ROOT)}; audit 1% at "
                         f"{loop['mc_sims']} sims, pooled, tolerance {audit_tol}; fallback "
                         f"per bettor at the strict size (every answer within 0.02) and, on the "
                         f"same rounds, at 10^4 sims; judge {judge_sims} sims",

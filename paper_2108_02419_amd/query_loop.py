@@ -66,7 +66,7 @@ def strict_sims(pooled, bound=0.02, z=STRICT_Z, lo=1024, hi=1 << 20):
 
 def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
         fallback_sims=25_000, judge_sims=1_000_000, gate=None, audit_tol=0.0175,
-        baseline_every=10, max_rounds=None, log=print, on_round=None):
+        baseline_every=10, max_rounds=None, log=print, on_round=None, cfg=None):
     """Steps the real race and answers every bettor each round.
 
     Each round: every bettor asks the surrogate (encode + forward, no
@@ -84,7 +84,9 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
     `fallbacks`.  A Monte-Carlo judge at
     `judge_sims` measures the error of every answer.  Every
     `baseline_every`-th round also times the plain Monte-Carlo path (every
-    bettor at `mc_sims`): the rate the system is compared with.
+    bettor at `mc_sims`): the rate the system is compared with.  `cfg`
+    (default inputs.CFG_QUERY) names the race: its seed, competitor count
+    and seconds per tick.
 
     `on_round`, when given, receives each round's host copies: the state
     (tick, pos, prev), the audited bettors and their request ids, their
@@ -92,7 +94,7 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
     judge's answer, the encoded features and slot map of every bettor, the
     surrogate's answers (float32 [bettors, 20], slot order) and, in fallback
     rounds, the fallback's answers."""
-    cfg = inputs.CFG_QUERY
+    cfg = inputs.CFG_QUERY if cfg is None else cfg
     q = inputs.query_race(cfg)
     comp, seed, real_req = q["comp"], q["seed"], q["real_request"]
     n = comp.shape[0]
@@ -130,6 +132,7 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
     rounds = []
     sur_s = audit_s = fb_s = base_s = 0.0
     base_q = 0
+    t_log = time.perf_counter()
     while max_rounds is None or len(rounds) < max_rounds:
         _bbe.race_advance(race, seed, real_req, 0, every, tick_t, pos_t, prev_t, state=state)
         torch.cuda.synchronize()
@@ -223,7 +226,8 @@ def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
                            audit_gap=audit_gap, flagged=flagged, sur_err=sur_err, mc_err=mc_err,
                            fallback_err=fb_err, answer_err=fb_err if flagged else sur_err,
                            t_sur=t_sur, t_audit=t_audit, t_fallback=t_fb, t_baseline=t_base))
-        if len(rounds) % 25 == 0:
+        if len(rounds) % 25 == 0 or time.perf_counter() - t_log > 30.0:
+            t_log = time.perf_counter()
             r = rounds[-1]
             log(f"round {len(rounds)} tick {tick} leader {r['leader']:.0f} sur_err "
                 f"{r['sur_err']:.4f} audit_gap {audit_gap:.4f} flagged {r['flagged']}")
@@ -275,6 +279,11 @@ def main():
     ap.add_argument("--params", required=True,
                     help="trained surrogate: a saved network (bbe_mlp_save) or parameters (.npy)")
     ap.add_argument("--every", type=int, default=1)
+    ap.add_argument("--dt", type=float, default=inputs.CFG_QUERY["dt"],
+                    help="seconds per tick of the race (its competitors' steps scale with it)")
+    ap.add_argument("--baseline-every", type=int, default=10)
+    ap.add_argument("--race-seed", type=int, default=inputs.CFG_QUERY["seed"],
+                    help="seed of the race's parameters and of its Monte-Carlo streams")
     ap.add_argument("--bettors", type=int, default=10_000)
     ap.add_argument("--fallback-sims", nargs="+", default=["25000"],
                     help="fallback simulations per bettor: numbers and/or 'strict'")
@@ -295,7 +304,9 @@ def main():
     fbs = [f if f == "strict" else int(f) for f in args.fallback_sims]
     res = run(net, every=args.every, n_bettors=args.bettors, fallback_sims=fbs,
               judge_sims=args.judge_sims, gate=args.gate, audit_tol=args.audit_tol,
-              max_rounds=args.max_rounds, log=lambda m: print(f"[query] {m}", flush=True))
+              max_rounds=args.max_rounds, baseline_every=args.baseline_every,
+              log=lambda m: print(f"[query] {m}", flush=True),
+              cfg=dict(inputs.CFG_QUERY, dt=args.dt, seed=args.race_seed))
     res["wall_s"] = time.perf_counter() - t0
     summary = {k: v for k, v in res.items() if k != "per_round"}
     print(json.dumps(summary), flush=True)

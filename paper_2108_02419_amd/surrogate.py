@@ -94,7 +94,7 @@ def mc_probs(ds: Dataset, n_sims: int, seed: int, request_base: int, stop_after:
     return probs, steps_total
 
 
-def encode(ds: Dataset, probs=None):
+def encode(ds: Dataset, probs=None, dt: float = DT):
     """Features (device int16-bits bf16 [B,160]), slot map and, with probs,
     slot-ordered targets."""
     B = len(ds)
@@ -106,7 +106,7 @@ def encode(ds: Dataset, probs=None):
     x = torch.empty((B, 160), dtype=torch.int16, device=dev)
     slot = torch.empty((B, 20), dtype=torch.int32, device=dev)
     target = torch.empty((B, 20), dtype=torch.float32, device=dev) if probs is not None else None
-    _bbe.encode_states(comp, n, pos, prev, L, DT, x, slot, probs, target)
+    _bbe.encode_states(comp, n, pos, prev, L, dt, x, slot, probs, target)
     return x, n, slot, target
 
 
@@ -118,7 +118,7 @@ class BlockStates:
     def __init__(self, block: int, seed: int, count: int = inputs.SURROGATE_BLOCK,
                  cfg: dict = inputs.CFG_SURROGATE):
         a = inputs.surrogate_state_block(block, count, cfg)
-        self.block, self.count = block, count
+        self.block, self.count, self.dt = block, count, float(cfg["dt"])
         self.n = a["n"]
         self.comp = a["comp"]
         self.races = [_bbe.Race(a["comp"][i, :a["n"][i]], L) for i in range(count)]
@@ -157,7 +157,7 @@ class BlockStates:
     def encode(self, x, slot=None, probs=None, target=None):
         """Features into x (int16 bits [count, 160]) and, with probs, the
         slot-ordered targets."""
-        _bbe.encode_states(self.comp_d, self.n_d, self.pos_d, self.prev_d, L, DT, x, slot,
+        _bbe.encode_states(self.comp_d, self.n_d, self.pos_d, self.prev_d, L, self.dt, x, slot,
                            probs, target)
 
 
@@ -173,19 +173,21 @@ def build_training_set(n_states: int, label_sims: int, seed: int, log=None, bloc
     n = torch.empty(n_states, dtype=torch.int32, device=dev)
     target = torch.empty((n_states, 20), dtype=torch.float32, device=dev)
     steps_total, mc_s = 0, 0.0
-    t0 = time.perf_counter()
+    t0 = t_log = time.perf_counter()
     for b, lo in enumerate(range(0, n_states, inputs.SURROGATE_BLOCK)):
         cnt = min(inputs.SURROGATE_BLOCK, n_states - lo)
         st = BlockStates(block0 + b, seed, cnt, cfg)
         t1 = time.perf_counter()
-        probs, steps = st.mc(label_sims, seed, request_base=lo)
+        probs, steps = st.mc(label_sims, seed, request_base=(block0 * inputs.SURROGATE_BLOCK
+                                                             + lo) & 0x7FFFFFFF)
         mc_s += time.perf_counter() - t1
         steps_total += steps
         st.encode(x[lo:lo + cnt], None, probs, target[lo:lo + cnt])
         n[lo:lo + cnt] = st.n_d
         torch.cuda.synchronize()
         del st, probs
-        if log and (b % 16 == 15 or lo + cnt == n_states):
+        if log and (b % 16 == 15 or lo + cnt == n_states or time.perf_counter() - t_log > 30):
+            t_log = time.perf_counter()
             log(f"labelled {lo + cnt}/{n_states} states ({time.perf_counter() - t0:.0f} s, "
                 f"Monte-Carlo {steps_total / max(mc_s, 1e-9):.3e} competitor-steps/s)")
     return x, n, target, steps_total, mc_s
@@ -319,28 +321,34 @@ def build_eval_set(n_states: int, judge_sims: int, seed: int, fallback_sims=(10_
 
 def train_and_judge(states=200_000, label_sims=2000, epochs=30, batch=4096, lr=2e-3, seed=4,
                     eval_states=2000, judge_sims=1_000_000, target_err=0.02, rp_sims=(4, 16, 64),
-                    fallback_sims=(10_000,), log=None):
-    """Generates states and Monte-Carlo labels, trains a network, judges it
-    on held-out states and calibrates its Monte-Carlo fallback gate (on the
-    first half of the held-out states; tested on the second half, with each
-    fallback size of fallback_sims).  Returns (network, result dict)."""
+                    fallback_sims=(10_000,), log=None, cfg: dict = inputs.CFG_SURROGATE,
+                    init=None, block0: int = 0, eval_block0: int = EVAL_BLOCK0):
+    """Generates states (blocks block0, block0 + 1, ... of the recipe `cfg`)
+    and Monte-Carlo labels, trains a network (from `init`, parameters, if
+    given), judges it on held-out states and calibrates its Monte-Carlo
+    fallback gate (on the first half of the held-out states; tested on the
+    second half, with each fallback size of fallback_sims).  Returns
+    (network, result dict)."""
     log = log or (lambda m: None)
-    x, n, target, steps, label_s = build_training_set(states, label_sims, seed, log)
+    x, n, target, steps, label_s = build_training_set(states, label_sims, seed, log,
+                                                      block0=block0, cfg=cfg)
     log(f"labels: {states} x {label_sims} sims, {steps} competitor-steps, {label_s:.1f} s "
         f"({steps / label_s:.3e} competitor-steps/s)")
-    net = _bbe.Mlp(inputs.surrogate_init(seed), max_batch=batch)
+    net = _bbe.Mlp(inputs.surrogate_init(seed) if init is None else init, max_batch=batch)
     t1 = time.perf_counter()
-    hist = train(net, x, n, target, epochs, batch, lr, log, shuffle_seed=seed)
+    hist = train(net, x, n, target, epochs, batch, lr, log, shuffle_seed=seed + block0)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t1
     del x, target
 
-    ex, en, jt, ans = build_eval_set(eval_states, judge_sims, seed, fallback_sims, rp_sims)
+    ex, en, jt, ans = build_eval_set(eval_states, judge_sims, seed, fallback_sims, rp_sims,
+                                     block0=eval_block0, cfg=cfg)
     pred, ent = predict(net, ex, en)
     torch.cuda.synchronize()
     half = eval_states // 2
     gate = calibrate_gate(pred[:half], ent[:half], jt[:half], en[:half], target_err)
-    res = dict(train_states=states, label_sims=label_sims, epochs=epochs, batch=batch, lr=lr,
+    res = dict(dt=cfg["dt"], block0=block0, from_init=init is not None,
+               train_states=states, label_sims=label_sims, epochs=epochs, batch=batch, lr=lr,
                train_seconds=train_s, label_seconds=label_s, label_competitor_steps=steps,
                loss_history=hist, eval_states=eval_states, judge_sims=judge_sims,
                surrogate_vs_judge=errors(pred, jt, en),
@@ -367,6 +375,13 @@ def main():
     ap.add_argument("--seed", type=int, default=4)
     ap.add_argument("--fallback-sims", type=int, nargs="+", default=[10_000, 25_000],
                     help="Monte-Carlo fallback sizes the gate is tested with")
+    ap.add_argument("--dt", type=float, default=inputs.CFG_SURROGATE["dt"],
+                    help="seconds per tick of the races (the competitors' steps scale with it)")
+    ap.add_argument("--block0", type=int, default=0,
+                    help="first block of training states (blocks of 65,536)")
+    ap.add_argument("--eval-block0", type=int, default=EVAL_BLOCK0)
+    ap.add_argument("--init", default=None,
+                    help="start from this network (bbe_mlp_save file or .npy parameters)")
     ap.add_argument("--out", default="bbe_out/surrogate")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
@@ -375,9 +390,15 @@ def main():
         print(f"[surrogate] {msg}", flush=True)
 
     torch.cuda.set_device(0)
+    init = None
+    if args.init:
+        init = (np.load(args.init) if args.init.endswith(".npy")
+                else _bbe.Mlp.load(args.init, max_batch=8).params())
+    cfg = dict(inputs.CFG_SURROGATE, dt=args.dt)
     net, res = train_and_judge(args.states, args.label_sims, args.epochs, args.batch, args.lr,
                                args.seed, args.eval_states, args.judge_sims, args.target_err,
-                               fallback_sims=tuple(args.fallback_sims), log=log)
+                               fallback_sims=tuple(args.fallback_sims), log=log, cfg=cfg,
+                               init=init, block0=args.block0, eval_block0=args.eval_block0)
     log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
     np.save(os.path.join(args.out, "params.npy"), net.params())
     net.save(os.path.join(args.out, "surrogate.bbemlp"))
