@@ -16,7 +16,9 @@ instruction count per competitor-step, and takes the HBM traffic per launch
 from the committed counter profile when that profile was taken on the
 current kernel sources; the cpu_baseline object times the
 CPU oracle on a bounded sample of the same workload (cpu_baselines_other:
-the other workloads, on bounded samples).  More objects measure the other
+the other workloads, on bounded samples).  `winner_only` times the same
+workload resolved only to each simulation's winner (the same win counts).
+More objects measure the other
 workloads of the path: `cfg0` (5 competitors, 10^3 simulations), `batch`
 (4096 uneven in-play requests in one graph-captured persistent launch),
 `surrogate` (queries per second of the surrogate network against
@@ -253,6 +255,32 @@ def main() -> int:
     assert int(counts.sum().item()) == n_sims * n
     del orders
 
+    # the same workload resolved only to its winner (stop_after = 1): the
+    # win counts and probabilities are the same as with the full order
+    wev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(8)]
+    w_steps = []
+    _bbe.race_sim(race, n_sims, c["seed"], request=c["request"], stop_after=c["stop_after"],
+                  wins=wins, steps=steps_t[0], stream=stream)
+    torch.cuda.synchronize()
+    wins_full = wins.clone()
+    for k, (ea, eb) in enumerate(wev):
+        ea.record(stream)
+        _bbe.race_sim(race, n_sims, c["seed"], request=c["request"], stop_after=1,
+                      wins=wins, steps=steps_t[0], stream=stream)
+        eb.record(stream)
+        torch.cuda.synchronize()
+        w_steps.append(int(steps_t[0].item()))
+    assert torch.equal(wins, wins_full)  # the same winners as the full order
+    w_ms = sorted(a.elapsed_time(b) for a, b in wev[1:])
+    w_med = w_ms[len(w_ms) // 2]
+    winner_only = {"workload": "mc_start_n20_1e6 resolved to the winner only (stop_after 1)",
+                   "kernel_ms": w_med, "sims_per_s": n_sims / (w_med / 1e3),
+                   "competitor_steps_per_launch": w_steps[-1],
+                   "competitor_steps_per_s": w_steps[-1] / (w_med / 1e3),
+                   "frac": w_steps[-1] * ALGO_OPS_PER_COMPETITOR_STEP / (w_med / 1e3)
+                   / VALU_PEAK_OPS}
+
     # the same workload with a time term in every competitor's responsiveness
     # (the paced kernel variant): kernel time and competitor-steps per second
     import numpy as np
@@ -299,6 +327,7 @@ def main() -> int:
         "kernel_ms": {"median": km[len(km) // 2], "mean": mean, "min": km[0], "cov": cov},
         "with_orders_kernel_ms": orders_ms,
         "rank_counts_ms": rank_counts_ms,
+        "winner_only": winner_only,
         "paced": paced,
         "wall_s": wall,
         "device": {"name": torch.cuda.get_device_name(0),
