@@ -14,6 +14,7 @@ bettor at the audit's size) is timed on a sample of rounds as the baseline.
 Orchestration only -- every computation runs in the library's kernels.
 
     python -m paper_2108_02419_amd.query_loop --params surrogate.bbemlp
+    python -m paper_2108_02419_amd.query_loop --params surrogate_dt01.bbemlp --dt 0.1 --every 10
 """
 from __future__ import annotations
 

@@ -9,6 +9,10 @@ map from an in-play state to those probabilities and is judged against a
 high-sample Monte-Carlo estimate.
 
     python -m paper_2108_02419_amd.surrogate --states 10000000 --label-sims 10000
+    python -m paper_2108_02419_amd.surrogate --dt 0.1 ...   # races of 0.1-second ticks
+
+A long run can be split into consecutive runs over new blocks of states,
+each starting from the previous network (--block0, --init).
 """
 from __future__ import annotations
 
