@@ -297,3 +297,30 @@ def test_work_list_cap_lengthens_items(torch, orc):
         assert torch.equal(wins[i, :race.n], w), i
         total += int(s.item())
     assert int(steps.item()) == total
+
+
+def test_batch_of_short_tick_races(torch, orc):
+    """A batch of races of 0.1-second ticks (the surrogate's second training
+    set and query loop): in-play states of the recipe at dt = 0.1, winner-only
+    and full-order requests, against the oracle request by request."""
+    a = inputs.surrogate_state_block(9000, 10, dict(inputs.CFG_SURROGATE, dt=0.1))
+    specs, exp_w, exp_s = [], [], 0
+    for i in range(10):
+        k = int(a["n"][i])
+        comp = a["comp"][i, :k]
+        st = orc.race_prefix(comp, L, SEED, int(a["prefix_request"][i]), 0, float(a["target"][i]))
+        stop = 1 if i % 3 else k
+        specs.append((Race(comp, L), st, 0, 150 + 37 * i, 7000 + i, stop))
+        _, w, s = orc.race_sim(comp, L, 150 + 37 * i, SEED, request=7000 + i, state=st,
+                               stop_after=stop, want_orders=False, threads=8)
+        exp_w.append(w)
+        exp_s += s
+    announce("batch of 10 requests at 0.1-second ticks")
+    plan, wins, probs, steps = _run_plan(torch, specs, SEED, autotune=False)
+    W = wins.cpu().numpy()
+    for i in range(10):
+        k = int(a["n"][i])
+        np.testing.assert_array_equal(W[i, :k].astype(np.uint64), exp_w[i], err_msg=f"request {i}")
+        assert (W[i, k:] == 0).all()
+    assert int(steps.item()) == exp_s
+    plan.free()

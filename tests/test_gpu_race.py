@@ -197,3 +197,14 @@ def test_fast_group_parks_early(torch, orc, n):
     tied = comp.copy()
     tied[fast] = [12.0, 12.0, 1.0, 0.0, 2.0]
     _compare(torch, orc, tied, 2000.0, 200, seed=n, request=5)
+
+
+@pytest.mark.parametrize("n", [5, 20])
+def test_races_of_short_ticks(torch, orc, n):
+    """Races of 0.1-second ticks (steps of 0.1-1.3 units, about 3000 ticks to
+    the line, blocking far more persistent than at 1-second ticks): full
+    orders from the start and the winner only from an in-play state."""
+    comp = inputs.competitor_params(np.random.default_rng(400 + n), n, 0.1)
+    _compare(torch, orc, comp, 2000.0, 640, 12, request=4)
+    st = orc.race_prefix(comp, 2000.0, 12, 0x80000000 | n, 0, np.float32(300.0))
+    _compare(torch, orc, comp, 2000.0, 700, 12, request=5, state=st, stop_after=1)
