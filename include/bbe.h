@@ -43,6 +43,16 @@ enum {
     BBE_ENOMEM = -2,   /* host or device allocation failed */
     BBE_EDEVICE = -3   /* a HIP call failed; message has the HIP error */
 };
+/* Every call reports failure by its return code and a message for
+ * bbe_last_error; a call that fails releases what it allocated and leaves
+ * the handles it was given usable.  For tests of these paths the library
+ * reads the environment variable BBE_FAULT_INJECT once per process:
+ * "alloc:K1,K2,..." makes the K-th device allocation of the process (counted
+ * from 1) fail as out of memory (BBE_ENOMEM), "device:K1,..." replaces the
+ * K-th counted HIP call (the uploads, launches, graph capture and graph
+ * launches of the entry points) by a failure without making it
+ * (BBE_EDEVICE); both may be given, separated by a space.  Unset, nothing
+ * is counted. */
 
 /* One competitor (paper Section 3, Eq. 1).
  *   lo, hi  free step law delta(v_c) = U(lo, hi) per tick, distance units;

@@ -40,6 +40,33 @@ inline int ok() {
     return BBE_OK;
 }
 
+// Host-side fault injection, for the tests of the error paths.  The
+// environment variable BBE_FAULT_INJECT, read once per process, names the
+// calls to fail: "alloc:K1,K2,..." fails the K-th device allocation made
+// through dev_alloc (counted from 1 over the process) as an out-of-memory
+// error, and "device:K1,..." replaces the K-th HIP call made through BBE_HIP
+// by a hipErrorLaunchFailure result without making it; the two may be
+// given together, separated by a space.  Unset, nothing is counted and
+// nothing fails.
+enum FaultKind { kFaultAlloc = 0, kFaultDevice = 1 };
+bool fault(FaultKind kind);
+
+inline hipError_t dev_alloc(void** p, size_t bytes) {
+    if (fault(kFaultAlloc)) {
+        *p = nullptr;
+        return hipErrorOutOfMemory;
+    }
+    return hipMalloc(p, bytes);
+}
+
+template <class T>
+inline hipError_t dev_alloc(T** p, size_t bytes) {
+    return dev_alloc(reinterpret_cast<void**>(p), bytes);
+}
+
+#define BBE_HIP(call) \
+    (::bbe_abi::fault(::bbe_abi::kFaultDevice) ? hipErrorLaunchFailure : (call))
+
 inline int hip_fail(hipError_t e, const char* what) {
     return fail(BBE_EDEVICE, "%s: %s (%s)", what, hipGetErrorName(e), hipGetErrorString(e));
 }

@@ -2,10 +2,69 @@
 // race handles, per-race constants, launch configuration and errors.
 #include "abi_internal.hpp"
 
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <new>
+#include <vector>
 
 namespace bbe_abi {
 thread_local std::string g_err;
+
+namespace {
+
+// The calls BBE_FAULT_INJECT names, per kind (sorted), and the running
+// count of each kind's calls.
+struct FaultPlan {
+    std::vector<uint64_t> at[2];
+    std::atomic<uint64_t> count[2];
+
+    FaultPlan() {
+        count[0] = 0;
+        count[1] = 0;
+        const char* env = std::getenv("BBE_FAULT_INJECT");
+        if (!env) return;
+        std::string spec(env);
+        size_t pos = 0;
+        while (pos < spec.size()) {
+            size_t end = spec.find(' ', pos);
+            if (end == std::string::npos) end = spec.size();
+            std::string item = spec.substr(pos, end - pos);
+            pos = end + 1;
+            size_t colon = item.find(':');
+            if (colon == std::string::npos) continue;
+            std::string kind = item.substr(0, colon);
+            int k = kind == "alloc" ? kFaultAlloc : kind == "device" ? kFaultDevice : -1;
+            if (k < 0) continue;
+            const char* p = item.c_str() + colon + 1;
+            while (*p) {
+                char* e = nullptr;
+                unsigned long long v = std::strtoull(p, &e, 10);
+                if (e == p) break;
+                if (v > 0) at[k].push_back(v);
+                p = (*e == ',') ? e + 1 : e;
+                if (*e != ',') break;
+            }
+            std::sort(at[k].begin(), at[k].end());
+        }
+    }
+};
+
+FaultPlan& fault_plan() {
+    static FaultPlan plan;
+    return plan;
+}
+
+}  // namespace
+
+bool fault(FaultKind kind) {
+    FaultPlan& plan = fault_plan();
+    const std::vector<uint64_t>& at = plan.at[kind];
+    if (at.empty()) return false;
+    const uint64_t n = plan.count[kind].fetch_add(1, std::memory_order_relaxed) + 1;
+    return std::binary_search(at.begin(), at.end(), n);
+}
+
 }  // namespace bbe_abi
 
 using namespace bbe_abi;
@@ -131,16 +190,16 @@ BBE_API int bbe_race_sim(const bbe_race* race, const bbe_state* state, uint32_t 
 
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipError_t e;
-    if (a.wins && (e = bbe::launch_zero_u64(a.wins, race->n, s)) != hipSuccess)
+    if (a.wins && (e = BBE_HIP(bbe::launch_zero_u64(a.wins, race->n, s))) != hipSuccess)
         return hip_fail(e, "zeroing win_counts");
-    if (a.steps && (e = bbe::launch_zero_u64(a.steps, 1, s)) != hipSuccess)
+    if (a.steps && (e = BBE_HIP(bbe::launch_zero_u64(a.steps, 1, s))) != hipSuccess)
         return hip_fail(e, "zeroing step_count");
 
     const int block = bbe::mc_block_size();
     uint64_t need = ((uint64_t)n_sims + block - 1) / block;
     uint64_t resident = (uint64_t)bbe::mc_blocks_per_cu(race->n, race->pace.paced != 0) * device_cus();
     int grid = (int)(need < resident ? need : resident);
-    if ((e = bbe::launch_race_mc(a, grid, s)) != hipSuccess)
+    if ((e = BBE_HIP(bbe::launch_race_mc(a, grid, s))) != hipSuccess)
         return hip_fail(e, "launching race_mc_kernel");
     return ok();
 }
@@ -152,9 +211,9 @@ BBE_API int bbe_win_probs(const uint64_t* win_counts, int n_rows, int n, int row
     if (n < 1 || n > BBE_MAX_COMPETITORS) return fail(BBE_EINVAL, "n = %d outside 1..%d", n,
                                                       BBE_MAX_COMPETITORS);
     if (row_stride < n) return fail(BBE_EINVAL, "row_stride must be >= n");
-    hipError_t e = bbe::launch_win_probs(reinterpret_cast<const unsigned long long*>(win_counts),
-                                         n_rows, n, row_stride, probs,
-                                         static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_win_probs(
+        reinterpret_cast<const unsigned long long*>(win_counts), n_rows, n, row_stride, probs,
+        static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching win_probs_kernel");
     return ok();
 }
@@ -164,9 +223,9 @@ BBE_API int bbe_rank_counts(const uint8_t* orders, uint32_t n_sims, int n, uint6
     if (n < 1 || n > BBE_MAX_COMPETITORS)
         return fail(BBE_EINVAL, "n = %d outside 1..%d", n, BBE_MAX_COMPETITORS);
     if (!counts || (!orders && n_sims > 0)) return fail(BBE_EINVAL, "NULL buffer");
-    hipError_t e = bbe::launch_rank_counts(orders, n_sims, n,
-                                           reinterpret_cast<unsigned long long*>(counts),
-                                           static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_rank_counts(
+        orders, n_sims, n, reinterpret_cast<unsigned long long*>(counts),
+        static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching rank_counts_kernel");
     return ok();
 }
@@ -178,9 +237,9 @@ BBE_API int bbe_order_pmf(const uint8_t* orders, uint32_t n_sims, int n, uint64_
     if (!counts || (!orders && n_sims > 0)) return fail(BBE_EINVAL, "NULL buffer");
     int n_fact = 1;
     for (int k = 2; k <= n; ++k) n_fact *= k;
-    hipError_t e = bbe::launch_order_pmf(orders, n_sims, n, n_fact,
-                                         reinterpret_cast<unsigned long long*>(counts),
-                                         static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_order_pmf(
+        orders, n_sims, n, n_fact, reinterpret_cast<unsigned long long*>(counts),
+        static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching order_pmf_kernel");
     return ok();
 }
@@ -207,7 +266,7 @@ BBE_API int bbe_race_prefix(const bbe_race* race, const bbe_state* state, uint64
     a.tick_out = tick_out;
     a.pos_out = pos_out;
     a.prev_out = prev_out;
-    hipError_t e = bbe::launch_race_prefix(a, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_race_prefix(a, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching race_prefix_kernel");
     return ok();
 }
@@ -234,7 +293,7 @@ BBE_API int bbe_race_advance(const bbe_race* race, const bbe_state* state, uint6
     a.tick_out = tick_out;
     a.pos_out = pos_out;
     a.prev_out = prev_out;
-    hipError_t e = bbe::launch_race_prefix(a, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_race_prefix(a, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching race_prefix_kernel");
     return ok();
 }

@@ -291,12 +291,12 @@ int upload_work(bbe_batch_plan* p, const Shape& sh, const std::vector<bbe::ReqDe
         if (p->d_chunks) (void)hipFree(p->d_chunks);
         p->d_chunks = nullptr;
         p->chunk_cap = 0;
-        if (hipMalloc(&p->d_chunks, w.chunks.size() * sizeof(bbe::Chunk)) != hipSuccess)
+        if (dev_alloc(&p->d_chunks, w.chunks.size() * sizeof(bbe::Chunk)) != hipSuccess)
             return fail(BBE_ENOMEM, "device allocation of the work list failed");
         p->chunk_cap = w.chunks.size();
     }
-    hipError_t e = hipMemcpy(p->d_chunks, w.chunks.data(), w.chunks.size() * sizeof(bbe::Chunk),
-                             hipMemcpyHostToDevice);
+    hipError_t e = BBE_HIP(hipMemcpy(p->d_chunks, w.chunks.data(),
+                                     w.chunks.size() * sizeof(bbe::Chunk), hipMemcpyHostToDevice));
     if (e != hipSuccess) return hip_fail(e, "copying the work list");
     p->n_chunks = (uint32_t)w.chunks.size();
     p->shape = sh;
@@ -384,17 +384,18 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
     (void)hipGetDevice(&p->device);
 
     hipError_t e;
-    if (hipMalloc(&p->d_reqs, sizeof(bbe::ReqDesc) * n_reqs) != hipSuccess ||
-        hipMalloc(&p->d_queue, sizeof(uint32_t) * bbe::kMaxN) != hipSuccess) {
+    if (dev_alloc(&p->d_reqs, sizeof(bbe::ReqDesc) * n_reqs) != hipSuccess ||
+        dev_alloc(&p->d_queue, sizeof(uint32_t) * bbe::kMaxN) != hipSuccess) {
         destroy(p);
         return fail(BBE_ENOMEM, "device allocation of the request table failed");
     }
-    if ((e = hipMemcpy(p->d_reqs, p->host_reqs.data(), sizeof(bbe::ReqDesc) * n_reqs,
-                       hipMemcpyHostToDevice)) != hipSuccess) {
+    if ((e = BBE_HIP(hipMemcpy(p->d_reqs, p->host_reqs.data(), sizeof(bbe::ReqDesc) * n_reqs,
+                               hipMemcpyHostToDevice))) != hipSuccess) {
         destroy(p);
         return hip_fail(e, "copying the request table");
     }
-    if ((e = hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking)) != hipSuccess) {
+    if ((e = BBE_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking))) !=
+        hipSuccess) {
         destroy(p);
         return hip_fail(e, "creating the capture stream");
     }
@@ -467,7 +468,7 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
     }
 
     // Capture clear -> queue reset -> persistent kernel -> probabilities.
-    if ((e = hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal)) !=
+    if ((e = BBE_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal))) !=
         hipSuccess) {
         destroy(p);
         return hip_fail(e, "beginning graph capture");
@@ -478,7 +479,8 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
         destroy(p);
         return hip_fail(ee != hipSuccess ? ee : e, "capturing the launch sequence");
     }
-    if ((e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0)) != hipSuccess) {
+    if ((e = BBE_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0))) !=
+        hipSuccess) {
         destroy(p);
         return hip_fail(e, "instantiating the graph");
     }
@@ -492,7 +494,7 @@ BBE_API int bbe_batch_plan_create(const bbe_request* reqs, int n_reqs, uint64_t 
 
 BBE_API int bbe_batch_plan_launch(bbe_batch_plan* plan, void* stream) {
     if (!plan || !plan->exec) return fail(BBE_EINVAL, "plan is NULL");
-    hipError_t e = hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(hipGraphLaunch(plan->exec, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching the plan graph");
     return ok();
 }
@@ -522,9 +524,9 @@ BBE_API int bbe_batch_plan_set_states(bbe_batch_plan* plan, const bbe_state* sta
     }
     // ordered after earlier launches on `stream`; the pageable source is
     // consumed before the call returns
-    hipError_t e = hipMemcpyAsync(plan->d_reqs, plan->host_reqs.data(),
-                                  sizeof(bbe::ReqDesc) * n_reqs, hipMemcpyHostToDevice,
-                                  static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(hipMemcpyAsync(plan->d_reqs, plan->host_reqs.data(),
+                                          sizeof(bbe::ReqDesc) * n_reqs, hipMemcpyHostToDevice,
+                                          static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "copying the request table");
     return ok();
 }
@@ -573,13 +575,14 @@ BBE_API int bbe_prefix_batch(const bbe_request* reqs, const uint32_t* sims, cons
         if (rc != BBE_OK) return rc;
     }
     bbe::ReqDesc* d = nullptr;
-    if (hipMalloc(&d, sizeof(bbe::ReqDesc) * n) != hipSuccess)
+    if (dev_alloc(&d, sizeof(bbe::ReqDesc) * n) != hipSuccess)
         return fail(BBE_ENOMEM, "device allocation failed");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipError_t e = hipMemcpyAsync(d, h.data(), sizeof(bbe::ReqDesc) * n, hipMemcpyHostToDevice, s);
+    hipError_t e =
+        BBE_HIP(hipMemcpyAsync(d, h.data(), sizeof(bbe::ReqDesc) * n, hipMemcpyHostToDevice, s));
     if (e == hipSuccess)
-        e = bbe::launch_prefix_batch(d, n, (uint32_t)seed, (uint32_t)(seed >> 32), tick_out,
-                                     pos_out, prev_out, s);
+        e = BBE_HIP(bbe::launch_prefix_batch(d, n, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                             tick_out, pos_out, prev_out, s));
     hipError_t e2 = hipStreamSynchronize(s);
     (void)hipFree(d);
     if (e != hipSuccess) return hip_fail(e, "in-play state batch");
@@ -644,13 +647,13 @@ BBE_API int bbe_prefix_batch_noalloc(const bbe_request* reqs, const uint32_t* si
             rc = fill_prefix_desc(reqs[i0 + j], sims[i0 + j], targets[i0 + j], i0 + j, h[j]);
             if (rc != BBE_OK) return rc;  // nothing launched yet; earlier pieces are unused
         }
-        hipError_t e = hipMemcpyAsync(d + i0, h, sizeof(bbe::ReqDesc) * m,
-                                      hipMemcpyHostToDevice, s);
+        hipError_t e = BBE_HIP(hipMemcpyAsync(d + i0, h, sizeof(bbe::ReqDesc) * m,
+                                              hipMemcpyHostToDevice, s));
         if (e == hipSuccess) e = hipStreamSynchronize(s);  // h is reused by the next piece
         if (e != hipSuccess) return hip_fail(e, "staging the request descriptors");
     }
-    hipError_t e = bbe::launch_prefix_batch(d, n, (uint32_t)seed, (uint32_t)(seed >> 32),
-                                            tick_out, pos_out, prev_out, s);
+    hipError_t e = BBE_HIP(bbe::launch_prefix_batch(d, n, (uint32_t)seed, (uint32_t)(seed >> 32),
+                                                    tick_out, pos_out, prev_out, s));
     hipError_t e2 = hipStreamSynchronize(s);
     if (e != hipSuccess) return hip_fail(e, "in-play state batch");
     if (e2 != hipSuccess) return hip_fail(e2, "in-play state batch");

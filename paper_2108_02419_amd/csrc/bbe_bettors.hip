@@ -45,7 +45,7 @@ BBE_API int bbe_race_trace(const bbe_race* race, const bbe_state* state, uint64_
     a.max_rows = max_rows;
     a.trace = trace;
     a.rows_out = n_rows;
-    hipError_t e = bbe::launch_race_trace(a, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_race_trace(a, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching race_trace_kernel");
     return ok();
 }
@@ -93,12 +93,13 @@ BBE_API int bbe_bettors_create(const uint8_t* kind, const float* param, int n_be
     b->n = (uint32_t)n_bettors;
     for (int i = 0; i < n_bettors; ++i) b->per_kind[kind[i]] += 1;
     const size_t nb = (size_t)n_bettors;
-    if (hipMalloc(&b->kind, nb) != hipSuccess || hipMalloc(&b->param, nb * sizeof(float)) != hipSuccess ||
-        hipMalloc(&b->id, nb * sizeof(uint32_t)) != hipSuccess) {
+    if (dev_alloc(&b->kind, nb) != hipSuccess ||
+        dev_alloc(&b->param, nb * sizeof(float)) != hipSuccess ||
+        dev_alloc(&b->id, nb * sizeof(uint32_t)) != hipSuccess) {
         destroy(b);
         return fail(BBE_ENOMEM, "device allocation of %d bettors failed", n_bettors);
     }
-    hipError_t e = hipMemcpy(b->kind, k.data(), nb, hipMemcpyHostToDevice);
+    hipError_t e = BBE_HIP(hipMemcpy(b->kind, k.data(), nb, hipMemcpyHostToDevice));
     if (e == hipSuccess) e = hipMemcpy(b->param, p.data(), nb * sizeof(float), hipMemcpyHostToDevice);
     if (e == hipSuccess)
         e = hipMemcpy(b->id, order.data(), nb * sizeof(uint32_t), hipMemcpyHostToDevice);
@@ -146,7 +147,7 @@ BBE_API int bbe_bettor_views(const bbe_bettors* b, const float* trace, uint32_t 
     a.k1 = (uint32_t)(seed >> 32);
     a.views = views;
     a.counts = counts;
-    hipError_t e = bbe::launch_bettor_views(a, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_bettor_views(a, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching bettor_views_kernel");
     return ok();
 }
@@ -159,9 +160,9 @@ BBE_API int bbe_rp_views(const uint64_t* wins, int n_bettors, int n, int row_str
     if (row_stride < n) return fail(BBE_EINVAL, "row_stride must be >= n");
     if (n_bettors < 0) return fail(BBE_EINVAL, "n_bettors must be >= 0");
     if (n_bettors > 0 && !wins) return fail(BBE_EINVAL, "wins is NULL");
-    hipError_t e = bbe::launch_rp_views(reinterpret_cast<const unsigned long long*>(wins),
+    hipError_t e = BBE_HIP(bbe::launch_rp_views(reinterpret_cast<const unsigned long long*>(wins),
                                         (uint32_t)n_bettors, n, row_stride, views, counts,
-                                        static_cast<hipStream_t>(stream));
+                                        static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching rp_views_kernel");
     return ok();
 }

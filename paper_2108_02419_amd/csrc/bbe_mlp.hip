@@ -42,7 +42,7 @@ void destroy(bbe_mlp* m) {
 
 template <typename T>
 bool alloc(T** p, size_t count) {
-    return hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T)) == hipSuccess;
+    return dev_alloc(p, count * sizeof(T)) == hipSuccess;
 }
 
 bbe::MlpAdamArgs adam_args(bbe_mlp* m, const float* grad, float lr) {
@@ -127,8 +127,8 @@ BBE_API int bbe_mlp_create(const float* params, int max_batch, bbe_mlp** out) {
         destroy(m);
         return fail(BBE_ENOMEM, "device allocation of the network failed");
     }
-    hipError_t e = hipMemcpy(m->params, params, sizeof(float) * bbe::kNParams,
-                             hipMemcpyHostToDevice);
+    hipError_t e = BBE_HIP(hipMemcpy(m->params, params, sizeof(float) * bbe::kNParams,
+                                     hipMemcpyHostToDevice));
     if (e == hipSuccess)
         e = hipMemcpy(m->tiles, tiles.data(), sizeof(bbe::WgradTile) * tiles.size(),
                       hipMemcpyHostToDevice);
@@ -206,7 +206,7 @@ BBE_API int bbe_mlp_forward(const bbe_mlp* m, const uint16_t* x, const int32_t* 
     a.probs = probs;
     a.entropy = entropy;
     a.logits = logits;
-    hipError_t e = bbe::launch_mlp_fwd(a, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_mlp_fwd(a, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching the forward pass");
     return ok();
 }
@@ -221,7 +221,7 @@ BBE_API int bbe_mlp_forward_hidden(const bbe_mlp* m, const uint16_t* x, const in
     a.h2 = hidden + layer;
     a.h3 = hidden + 2 * layer;
     a.logits = logits;
-    hipError_t e = bbe::launch_mlp_fwd(a, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_mlp_fwd(a, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching the forward pass");
     return ok();
 }
@@ -234,7 +234,7 @@ BBE_API int bbe_mlp_loss_grad(bbe_mlp* m, const uint16_t* x, const int32_t* n_va
         return fail(BBE_EINVAL, "batch must be in 1..%d", m->max_batch);
     hipStream_t s = static_cast<hipStream_t>(stream);
     float* g = grad ? grad : m->grad;
-    hipError_t e = bbe::launch_fill_f32(loss, 0.0f, 1, s);
+    hipError_t e = BBE_HIP(bbe::launch_fill_f32(loss, 0.0f, 1, s));
     if (e == hipSuccess) e = bbe::launch_fill_f32(g, 0.0f, bbe::kNParams, s);
     bbe::MlpFwdArgs f = fwd_args(m, x, n_valid, batch);
     f.h1 = m->h1;
@@ -278,8 +278,8 @@ BBE_API int bbe_mlp_adam_step(bbe_mlp* m, const float* grad, float lr, void* str
     if (!m) return fail(BBE_EINVAL, "NULL network");
     if (!std::isfinite(lr) || !(lr > 0.0f)) return fail(BBE_EINVAL, "lr must be finite and > 0");
     m->step += 1;
-    hipError_t e = bbe::launch_mlp_adam(adam_args(m, grad ? grad : m->grad, lr),
-                                        static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_mlp_adam(adam_args(m, grad ? grad : m->grad, lr),
+                                        static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching the Adam step");
     return ok();
 }
@@ -318,7 +318,7 @@ BBE_API int bbe_encode_states(const float* comp, const int32_t* n, const float* 
     a.slot = slot_comp;
     a.probs_in = probs;
     a.target = target;
-    hipError_t e = bbe::launch_encode(a, static_cast<hipStream_t>(stream));
+    hipError_t e = BBE_HIP(bbe::launch_encode(a, static_cast<hipStream_t>(stream)));
     if (e != hipSuccess) return hip_fail(e, "launching the encoder");
     return ok();
 }
