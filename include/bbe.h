@@ -445,9 +445,21 @@ int bbe_mlp_get_params(const bbe_mlp *m, float *params);
  * Errors: BBE_EINVAL (NULL argument, file not writable), BBE_EDEVICE.       */
 int bbe_mlp_save(const bbe_mlp *m, const char *path);
 
+/* Saves a training checkpoint to a file (host path): the 8 bytes
+ * "BBEMLP02", the parameter count as uint32 and the number of Adam steps
+ * taken as uint64 (little endian), then the float32 parameters, the Adam
+ * first moments and the Adam second moments, each in the packing above.
+ * Training resumed from it takes the same steps, bit for bit, as training
+ * that did not stop.  Synchronous: call it once the network's last training
+ * step has completed on its stream.
+ * Errors: BBE_EINVAL (NULL argument, file not writable), BBE_EDEVICE.       */
+int bbe_mlp_save_checkpoint(const bbe_mlp *m, const char *path);
+
 /* Creates a network (as bbe_mlp_create, with max_batch) from a file written
- * by bbe_mlp_save.  Errors: BBE_EINVAL (missing or malformed file, or what
- * bbe_mlp_create rejects), BBE_ENOMEM, BBE_EDEVICE.                          */
+ * by bbe_mlp_save (Adam state zero, no steps taken) or by
+ * bbe_mlp_save_checkpoint (Adam state and step count restored).
+ * Errors: BBE_EINVAL (missing or malformed file, or what bbe_mlp_create
+ * rejects), BBE_ENOMEM, BBE_EDEVICE.                                         */
 int bbe_mlp_load(const char *path, int max_batch, bbe_mlp **out);
 
 /* Inference on `batch` rows (any size).  Device outputs, each optional:

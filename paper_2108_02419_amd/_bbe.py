@@ -72,6 +72,7 @@ SIGNATURES = {
     "bbe_mlp_free": (None, [_P]),
     "bbe_mlp_get_params": (_I, [_P, _P]),
     "bbe_mlp_save": (_I, [_P, ctypes.c_char_p]),
+    "bbe_mlp_save_checkpoint": (_I, [_P, ctypes.c_char_p]),
     "bbe_mlp_load": (_I, [ctypes.c_char_p, _I, _P]),
     "bbe_mlp_forward": (_I, [_P, _P, _P, _I, _P, _P, _P, _P]),
     "bbe_mlp_forward_hidden": (_I, [_P, _P, _P, _I, _P, _P, _P]),
@@ -396,6 +397,11 @@ class Mlp:
 
     def save(self, path: str):
         _check(lib().bbe_mlp_save(self._h, os.fsencode(path)))
+
+    def save_checkpoint(self, path: str):
+        """``bbe_mlp_save_checkpoint``: parameters, Adam moments and step
+        count (``load`` resumes training from it exactly)."""
+        _check(lib().bbe_mlp_save_checkpoint(self._h, os.fsencode(path)))
 
     @classmethod
     def load(cls, path: str, max_batch: int) -> "Mlp":

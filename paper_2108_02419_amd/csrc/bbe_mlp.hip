@@ -157,10 +157,13 @@ BBE_API int bbe_mlp_get_params(const bbe_mlp* m, float* params) {
     return ok();
 }
 
-// File layout: 8-byte magic "BBEMLP01", uint32 parameter count (little
-// endian), then the float32 master parameters in the packing of
-// BBE_MLP_NPARAMS.
+// File layouts (little endian): parameters only -- 8-byte magic
+// "BBEMLP01", uint32 parameter count, the float32 master parameters in the
+// packing of BBE_MLP_NPARAMS; training checkpoint -- magic "BBEMLP02",
+// uint32 parameter count, uint64 Adam steps taken, then parameters, Adam
+// first moments and Adam second moments (float32, same packing).
 static const char kMagic[8] = {'B', 'B', 'E', 'M', 'L', 'P', '0', '1'};
+static const char kMagicCkpt[8] = {'B', 'B', 'E', 'M', 'L', 'P', '0', '2'};
 
 BBE_API int bbe_mlp_save(const bbe_mlp* m, const char* path) {
     if (!m || !path) return fail(BBE_EINVAL, "NULL argument");
@@ -177,6 +180,28 @@ BBE_API int bbe_mlp_save(const bbe_mlp* m, const char* path) {
     return ok();
 }
 
+BBE_API int bbe_mlp_save_checkpoint(const bbe_mlp* m, const char* path) {
+    if (!m || !path) return fail(BBE_EINVAL, "NULL argument");
+    const size_t np = (size_t)bbe::kNParams;
+    std::vector<float> buf(3 * np);
+    const float* src[3] = {m->params, m->m, m->v};
+    for (int i = 0; i < 3; ++i) {
+        hipError_t e = BBE_HIP(hipMemcpy(buf.data() + i * np, src[i], sizeof(float) * np,
+                                         hipMemcpyDeviceToHost));
+        if (e != hipSuccess) return hip_fail(e, "copying the training state");
+    }
+    FILE* f = std::fopen(path, "wb");
+    if (!f) return fail(BBE_EINVAL, "cannot open %s for writing", path);
+    const uint32_t count = (uint32_t)bbe::kNParams;
+    const uint64_t step = (uint64_t)m->step;
+    bool good = std::fwrite(kMagicCkpt, 1, 8, f) == 8 && std::fwrite(&count, 4, 1, f) == 1 &&
+                std::fwrite(&step, 8, 1, f) == 1 &&
+                std::fwrite(buf.data(), sizeof(float), buf.size(), f) == buf.size();
+    good = (std::fclose(f) == 0) && good;
+    if (!good) return fail(BBE_EINVAL, "writing %s failed", path);
+    return ok();
+}
+
 BBE_API int bbe_mlp_load(const char* path, int max_batch, bbe_mlp** out) {
     if (!out) return fail(BBE_EINVAL, "out is NULL");
     *out = nullptr;
@@ -185,16 +210,40 @@ BBE_API int bbe_mlp_load(const char* path, int max_batch, bbe_mlp** out) {
     if (!f) return fail(BBE_EINVAL, "cannot open %s", path);
     char magic[8];
     uint32_t count = 0;
-    std::vector<float> p((size_t)bbe::kNParams);
-    bool good = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMagic, 8) == 0 &&
-                std::fread(&count, 4, 1, f) == 1 && count == (uint32_t)bbe::kNParams &&
-                std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
+    uint64_t step = 0;
+    const size_t np = (size_t)bbe::kNParams;
+    bool good = std::fread(magic, 1, 8, f) == 8;
+    const bool ckpt = good && std::memcmp(magic, kMagicCkpt, 8) == 0;
+    good = good && (ckpt || std::memcmp(magic, kMagic, 8) == 0) &&
+           std::fread(&count, 4, 1, f) == 1 && count == (uint32_t)bbe::kNParams;
+    if (good && ckpt) good = std::fread(&step, 8, 1, f) == 1;
+    std::vector<float> p((ckpt ? 3 : 1) * np);
+    good = good && std::fread(p.data(), sizeof(float), p.size(), f) == p.size();
     char extra;
-    good = good && std::fread(&extra, 1, 1, f) == 0;  // nothing after the parameters
+    good = good && std::fread(&extra, 1, 1, f) == 0;  // nothing after the data
     std::fclose(f);
     if (!good) return fail(BBE_EINVAL, "%s is not a saved network of %d parameters", path,
                            bbe::kNParams);
-    return bbe_mlp_create(p.data(), max_batch, out);
+    if (ckpt)
+        for (size_t i = np; i < 3 * np; ++i)
+            if (!std::isfinite(p[i]) || (i >= 2 * np && p[i] < 0.0f))
+                return fail(BBE_EINVAL, "%s: Adam moment %zu is not valid", path, i - np);
+    bbe_mlp* m = nullptr;
+    int rc = bbe_mlp_create(p.data(), max_batch, &m);
+    if (rc != BBE_OK) return rc;
+    if (ckpt) {
+        hipError_t e = BBE_HIP(hipMemcpy(m->m, p.data() + np, sizeof(float) * np,
+                                         hipMemcpyHostToDevice));
+        if (e == hipSuccess)
+            e = hipMemcpy(m->v, p.data() + 2 * np, sizeof(float) * np, hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            destroy(m);
+            return hip_fail(e, "restoring the Adam state");
+        }
+        m->step = (long)step;
+    }
+    *out = m;
+    return ok();
 }
 
 BBE_API int bbe_mlp_forward(const bbe_mlp* m, const uint16_t* x, const int32_t* n_valid,

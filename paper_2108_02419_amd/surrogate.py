@@ -338,7 +338,10 @@ def train_and_judge(states=200_000, label_sims=2000, epochs=30, batch=4096, lr=2
                                                       block0=block0, cfg=cfg)
     log(f"labels: {states} x {label_sims} sims, {steps} competitor-steps, {label_s:.1f} s "
         f"({steps / label_s:.3e} competitor-steps/s)")
-    net = _bbe.Mlp(inputs.surrogate_init(seed) if init is None else init, max_batch=batch)
+    if isinstance(init, str):  # a saved network or training checkpoint
+        net = _bbe.Mlp.load(init, max_batch=batch)
+    else:
+        net = _bbe.Mlp(inputs.surrogate_init(seed) if init is None else init, max_batch=batch)
     t1 = time.perf_counter()
     hist = train(net, x, n, target, epochs, batch, lr, log, shuffle_seed=seed + block0)
     torch.cuda.synchronize()
@@ -385,7 +388,8 @@ def main():
                     help="first block of training states (blocks of 65,536)")
     ap.add_argument("--eval-block0", type=int, default=EVAL_BLOCK0)
     ap.add_argument("--init", default=None,
-                    help="start from this network (bbe_mlp_save file or .npy parameters)")
+                    help="start from this network: .npy parameters, a saved network, or a "
+                         "training checkpoint (Adam state restored)")
     ap.add_argument("--out", default="bbe_out/surrogate")
     args = ap.parse_args()
     os.makedirs(args.out, exist_ok=True)
@@ -395,9 +399,8 @@ def main():
 
     torch.cuda.set_device(0)
     init = None
-    if args.init:
-        init = (np.load(args.init) if args.init.endswith(".npy")
-                else _bbe.Mlp.load(args.init, max_batch=8).params())
+    if args.init:  # .npy parameters, or a saved network / training checkpoint
+        init = np.load(args.init) if args.init.endswith(".npy") else args.init
     cfg = dict(inputs.CFG_SURROGATE, dt=args.dt)
     net, res = train_and_judge(args.states, args.label_sims, args.epochs, args.batch, args.lr,
                                args.seed, args.eval_states, args.judge_sims, args.target_err,
@@ -406,6 +409,7 @@ def main():
     log(json.dumps({k: v for k, v in res.items() if k != "loss_history"}))
     np.save(os.path.join(args.out, "params.npy"), net.params())
     net.save(os.path.join(args.out, "surrogate.bbemlp"))
+    net.save_checkpoint(os.path.join(args.out, "checkpoint.bbemlp"))
     with open(os.path.join(args.out, "result.json"), "w") as f:
         json.dump(res, f, indent=1)
 

@@ -236,11 +236,27 @@ def test_mlp_load_rejects_bad_files(L, tmp_path):
     wrong_count.write_bytes(b"BBEMLP01" + (5).to_bytes(4, "little") + bytes(20))
     longer = tmp_path / "long.bin"
     longer.write_bytes(b"BBEMLP01" + (177940).to_bytes(4, "little") + bytes(4 * 177940 + 1))
-    for f in (bad_magic, short, wrong_count, longer):
+    # training checkpoints: magic, count, step, then parameters and both
+    # Adam moments; short files and invalid moments are rejected before any
+    # device work
+    np_ = 177940
+    head = b"BBEMLP02" + np_.to_bytes(4, "little") + (7).to_bytes(8, "little")
+    ck_short = tmp_path / "ck_short.bin"
+    ck_short.write_bytes(head + bytes(4 * 2 * np_))
+    ck_nan = tmp_path / "ck_nan.bin"
+    m = np.zeros(3 * np_, np.float32)
+    m[np_ + 5] = np.nan
+    ck_nan.write_bytes(head + m.tobytes())
+    ck_neg = tmp_path / "ck_neg.bin"
+    m = np.zeros(3 * np_, np.float32)
+    m[2 * np_ + 9] = -1e-3  # a second moment below zero
+    ck_neg.write_bytes(head + m.tobytes())
+    for f in (bad_magic, short, wrong_count, longer, ck_short, ck_nan, ck_neg):
         assert L.bbe_mlp_load(str(f).encode(), 8, ctypes.byref(out)) == _bbe.EINVAL, f
         assert L.bbe_last_error().decode()
     assert L.bbe_mlp_load(None, 8, ctypes.byref(out)) == _bbe.EINVAL
     assert L.bbe_mlp_save(None, b"/tmp/x") == _bbe.EINVAL
+    assert L.bbe_mlp_save_checkpoint(None, b"/tmp/x") == _bbe.EINVAL
 
 
 def test_prefix_batch_noalloc_rejects_before_device_work(L):

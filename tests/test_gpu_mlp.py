@@ -331,3 +331,46 @@ def test_save_and_load_round_trip(torch, tmp_path):
         torch.cuda.synchronize()
         outs.append(probs.cpu().numpy())
     np.testing.assert_array_equal(outs[0], outs[1])
+
+
+def test_checkpoint_resumes_training_exactly(torch, tmp_path):
+    """Six training steps on six minibatches straight through, and three
+    steps, a checkpoint, a fresh network loaded from it and the last three
+    steps: the two checkpoints after six steps are the same bytes
+    (parameters, both Adam moments, step count).  Loading the parameters
+    alone (Adam state reset) gives a different network."""
+    rng = np.random.default_rng(21)
+    B = 300
+    batches = []
+    for _ in range(6):
+        X, n, T = _features(rng, B)
+        batches.append((_bits(torch, X), torch.tensor(n, device="cuda"),
+                        torch.tensor(T, device="cuda")))
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    params = inputs.surrogate_random(6)
+    announce("mlp checkpoint resume")
+
+    def steps(net, bs):
+        for xt, nt, tt in bs:
+            net.train_step(xt, nt, tt, 2e-3, loss)
+        torch.cuda.synchronize()
+
+    a = _bbe.Mlp(params, max_batch=B)
+    steps(a, batches)
+    a.save_checkpoint(str(tmp_path / "a.ckpt"))
+
+    b = _bbe.Mlp(params, max_batch=B)
+    steps(b, batches[:3])
+    b.save_checkpoint(str(tmp_path / "b3.ckpt"))
+    b.save(str(tmp_path / "b3.params"))
+    c = _bbe.Mlp.load(str(tmp_path / "b3.ckpt"), max_batch=B)
+    steps(c, batches[3:])
+    c.save_checkpoint(str(tmp_path / "c.ckpt"))
+    raw_a = open(tmp_path / "a.ckpt", "rb").read()
+    assert raw_a[:8] == b"BBEMLP02" and len(raw_a) == 8 + 4 + 8 + 3 * 4 * ref.N_PARAMS
+    assert int(np.frombuffer(raw_a[12:20], "<u8")[0]) == 6
+    assert raw_a == open(tmp_path / "c.ckpt", "rb").read()
+
+    d = _bbe.Mlp.load(str(tmp_path / "b3.params"), max_batch=B)
+    steps(d, batches[3:])
+    assert not np.array_equal(d.params(), a.params())
