@@ -66,7 +66,7 @@ def strict_sims(pooled, bound=0.02, z=STRICT_Z, lo=1024, hi=1 << 20):
 
 
 def run(params, every=1, n_bettors=10_000, audit_frac=0.01, mc_sims=10_000,
-        fallback_sims=25_000, judge_sims=1_000_000, gate=None, audit_tol=0.0175,
+        fallback_sims="strict", judge_sims=1_000_000, gate=None, audit_tol=0.0175,
         baseline_every=10, max_rounds=None, log=print, on_round=None, cfg=None):
     """Steps the real race and answers every bettor each round.
 
@@ -286,7 +286,7 @@ def main():
     ap.add_argument("--race-seed", type=int, default=inputs.CFG_QUERY["seed"],
                     help="seed of the race's parameters and of its Monte-Carlo streams")
     ap.add_argument("--bettors", type=int, default=10_000)
-    ap.add_argument("--fallback-sims", nargs="+", default=["25000"],
+    ap.add_argument("--fallback-sims", nargs="+", default=["strict"],
                     help="fallback simulations per bettor: numbers and/or 'strict'")
     ap.add_argument("--judge-sims", type=int, default=1_000_000)
     ap.add_argument("--audit-tol", type=float, default=0.0175)
