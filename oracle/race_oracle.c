@@ -11,7 +11,7 @@
  *
  * What is computed (paper Section 3 and Eq. 1):
  *   - a race is n competitors on a 1-D track of length L; the state is the
- *     vector of positions d(t) (Section 3, "the state of the race");
+ *     vector of positions d(t) (Section 3 takes it as the race's state);
  *   - each tick every running competitor advances by S_c(t) > 0 computed from
  *     the start-of-tick state (Section 3, d_c(t+dt) = d_c(t) + S_c(t));
  *   - S_c follows Eq. 1: R_c * P_c * delta(v_c) when the nearest competitor
