@@ -145,24 +145,27 @@ def _slot_to_comp(sp, slot, n):
     return out
 
 
-@pytest.mark.parametrize("gate", [-1.0, 1e9], ids=["fallback", "served"])
-def test_query_loop_end_to_end(torch, orc, gate):
-    """Three rounds, 7 ticks apart, 300 bettors: the watched race, the 1%
-    audit's Monte-Carlo answers and their pooled estimate, the fallback's
+@pytest.mark.parametrize("gate,dt,every", [(-1.0, 1.0, 7), (1e9, 1.0, 7), (-1.0, 0.1, 10)],
+                         ids=["fallback", "served", "fallback_dt01"])
+def test_query_loop_end_to_end(torch, orc, gate, dt, every):
+    """Three rounds, `every` ticks apart, 300 bettors: the watched race, the
+    1% audit's Monte-Carlo answers and their pooled estimate, the fallback's
     answers (sampled) and the judge against the oracle bit for bit, the
     surrogate's inputs bit for bit and its answers against the reference
     network.  gate -1 sends every round to the fallback; 1e9 (with an audit
-    tolerance of 1) serves every round from the surrogate."""
-    q = inputs.query_race()
+    tolerance of 1) serves every round from the surrogate; dt 0.1 is the
+    same race with 0.1-second ticks."""
+    cfg = dict(inputs.CFG_QUERY, dt=dt)
+    q = inputs.query_race(cfg)
     comp, seed, real = q["comp"], q["seed"], q["real_request"]
     n = comp.shape[0]
     params = inputs.surrogate_random(8)
     rounds = []
-    announce(f"query loop gate={gate}")
-    res = query_loop.run(params, every=7, n_bettors=300, mc_sims=400,
+    announce(f"query loop gate={gate} dt={dt}")
+    res = query_loop.run(params, every=every, n_bettors=300, mc_sims=400,
                          fallback_sims=[300, "strict"], judge_sims=3000, gate=gate,
                          audit_tol=1.0, baseline_every=2, max_rounds=3, log=lambda m: None,
-                         on_round=rounds.append)
+                         on_round=rounds.append, cfg=cfg)
     assert res["rounds"] == 3 and len(rounds) == 3
     assert res["flagged_rounds"] == (3 if gate < 0 else 0)
     trace = orc.race_trace(comp, L, seed, real, 0, 40)
@@ -171,8 +174,8 @@ def test_query_loop_end_to_end(torch, orc, gate):
     comp_b[0, :n] = comp
     for k, rd in enumerate(rounds):
         tick, pos, prev = rd["state"]
-        want = _oracle_state_at(orc, comp, seed, real, 7 * (k + 1), trace)
-        assert tick == want[0] == 7 * (k + 1)
+        want = _oracle_state_at(orc, comp, seed, real, every * (k + 1), trace)
+        assert tick == want[0] == every * (k + 1)
         np.testing.assert_array_equal(pos, want[1])
         np.testing.assert_array_equal(prev, want[2])
         # the audit: 1% of the bettors, each its own request, pooled
@@ -190,7 +193,7 @@ def test_query_loop_end_to_end(torch, orc, gate):
                                 state=rd["state"], stop_after=1, want_orders=False, threads=8)
         np.testing.assert_array_equal(rd["judge"], orc.win_probs(wj))
         # surrogate: every bettor sees the same state, encoded as the oracle does
-        X, slot = ref.encode(comp_b, [n], pos[None, :], prev[None, :], L, inputs.CFG_QUERY["dt"])
+        X, slot = ref.encode(comp_b, [n], pos[None, :], prev[None, :], L, dt)
         want_x = (ref.bf16(X).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
         xs = rd["x"].view(np.uint16)
         assert (xs == want_x[0][None, :]).all()
