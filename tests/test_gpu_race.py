@@ -208,3 +208,22 @@ def test_races_of_short_ticks(torch, orc, n):
     _compare(torch, orc, comp, 2000.0, 640, 12, request=4)
     st = orc.race_prefix(comp, 2000.0, 12, 0x80000000 | n, 0, np.float32(300.0))
     _compare(torch, orc, comp, 2000.0, 700, 12, request=5, state=st, stop_after=1)
+
+
+@pytest.mark.parametrize("a,b", [((10.0, 20.0), (1.0, 25.0)), ((10.0, 20.0), (11.0, 19.0))],
+                         ids=["paper_example", "close_race"])
+def test_two_competitor_law_at_1e8_sims(torch, a, b):
+    """Two non-interacting competitors (theta = 0, rho = 0) on a 2000-unit
+    track, the first pair being the paper's example step laws U(10,20) and
+    U(1,25): 10^8 GPU simulations against the continuous winner law
+    computed by numerical integration (oracle/twocomp.py), within 5 sigma
+    (sigma 3e-6 for the paper's pair, 5e-5 for the close one)."""
+    from oracle.twocomp import p_first_wins_continuous
+    p = p_first_wins_continuous(a, b, 2000.0)
+    comp = np.array([[a[0], a[1], 1, 0, 0], [b[0], b[1], 1, 0, 0]], np.float32)
+    N = 100_000_000
+    announce(f"two-competitor law {a} vs {b}, {N} sims")
+    _, w, _ = _gpu_mc(torch, comp, 2000.0, N, 21, request=3, stop_after=1, orders=False)
+    assert int(w.sum()) == N
+    sig = np.sqrt(p * (1 - p) / N)
+    assert abs(w[0] / N - p) <= 5 * sig, (w[0] / N, p, sig)

@@ -26,3 +26,29 @@ def test_two_competitor_law(orc, name, a, b, K):
     ph = wins[0] / N
     sig = np.sqrt(max(p * (1 - p), 1.0 / N) / N)
     assert abs(ph - p) <= 5 * sig, (ph, p, sig)
+
+
+def test_continuous_law_symmetry_and_complement():
+    """The continuous winner law (a numerical integration apart from the
+    simulation code): equal step laws give 1/2, and swapping the two
+    competitors gives the complement (equal fractions have probability 0)."""
+    from oracle.twocomp import p_first_wins_continuous
+    assert abs(p_first_wins_continuous((10.0, 20.0), (10.0, 20.0), 2000.0) - 0.5) < 1e-6
+    ab = p_first_wins_continuous((10.0, 20.0), (11.0, 19.0), 2000.0)
+    ba = p_first_wins_continuous((11.0, 19.0), (10.0, 20.0), 2000.0)
+    assert abs(ab + ba - 1.0) < 1e-6
+
+
+@pytest.mark.parametrize("a,b", [((10.0, 20.0), (1.0, 25.0)), ((10.0, 20.0), (11.0, 19.0))],
+                         ids=["paper_example", "close_race"])
+def test_oracle_with_16_bit_draws_against_continuous_law(orc, a, b):
+    """The oracle's own draw resolution (16 bits, levels = 0) against the
+    continuous law at 10^6 simulations, within 5 sigma."""
+    from oracle.twocomp import p_first_wins_continuous
+    L = 2000.0
+    p = p_first_wins_continuous(a, b, L)
+    comp = np.array([[a[0], a[1], 1, 0, 0], [b[0], b[1], 1, 0, 0]], np.float32)
+    N = 1_000_000
+    _, wins, _ = orc.race_sim(comp, L, N, seed=12, stop_after=1, want_orders=False, threads=8)
+    sig = np.sqrt(max(p * (1 - p), 1.0 / N) / N)
+    assert abs(wins[0] / N - p) <= 5 * sig, (wins[0] / N, p, sig)
