@@ -29,13 +29,15 @@ __device__ __forceinline__ unsigned long long wave_sum_u64b(unsigned long long v
     return v;
 }
 
-// Parked slots stop being stepped 4 at a time once every lane has parked
-// them, from N = 12 on.  From N = 18 on, the copies of the tick fit in the
-// registers only with ranking and parking in one pass (slots_rank_park);
-// the paced variant spills even so and keeps N = 12 .. 17.
+// Parked slots stop being stepped 2 at a time once every lane has parked
+// them, from N = 6 on.  From N = 18 on, the copies of the tick fit in the
+// registers only with ranking and parking in one pass (slots_rank_park).
+// The paced variant skips 4 at a time for N = 12 .. 17 only: it spills
+// from N = 18 on either way.
 template <int N, bool kPaced>
 constexpr int batch_skip_step() {
-    return (N >= 12 && (!kPaced || N <= 17)) ? 4 : 0;
+    if constexpr (kPaced) return (N >= 12 && N <= 17) ? 4 : 0;
+    return N >= 6 ? 2 : 0;
 }
 
 template <int N, bool kPaced>

@@ -56,12 +56,12 @@ constexpr int mc_waves_per_eu() {
     return 4;
 }
 
-// Parked slots stop being stepped 4 at a time once every lane has parked
-// them (from N = 12 on; smaller races gain too little for the extra copies
+// Parked slots stop being stepped 2 at a time once every lane has parked
+// them (from N = 6 on; smaller races gain too little for the extra copies
 // of the tick).
 template <int N>
 constexpr int mc_skip_step() {
-    return N >= 12 ? 4 : 0;
+    return N >= 6 ? 2 : 0;
 }
 
 template <int N, bool kPaced>
