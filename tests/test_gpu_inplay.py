@@ -287,3 +287,46 @@ def test_rp_bettor_loop_end_to_end(torch, orc):
         np.testing.assert_array_equal(rd["cheap_counts"].astype(np.uint32), cc[0])
     assert res["dry_runs"] == 3 * int(d.sum())
     assert res["competitor_steps"] == total_steps
+
+
+def test_query_loop_full_size_sampled(torch, orc):
+    """The query loop at the size bench.py times (10^4 bettors, 10^4
+    simulations per audited and per fallback answer, a 10^6-simulation
+    judge), two rounds with every round handed back: sampled audit and
+    fallback answers against the oracle one by one, every bettor's
+    features bit for bit, and the surrogate's answer against the reference
+    network."""
+    q = inputs.query_race()
+    comp, seed, real = q["comp"], q["seed"], q["real_request"]
+    n = comp.shape[0]
+    params = inputs.surrogate_random(9)
+    rounds = []
+    announce("query loop full size, 2 rounds")
+    res = query_loop.run(params, every=1, n_bettors=10_000, mc_sims=10_000,
+                         fallback_sims=[10_000], judge_sims=1_000_000, gate=-1.0,
+                         baseline_every=0, max_rounds=2, log=lambda m: None,
+                         on_round=rounds.append)
+    assert res["rounds"] == 2 and res["flagged_rounds"] == 2
+    rng = np.random.default_rng(7)
+    comp_b = np.zeros((1, 20, 5), np.float32)
+    comp_b[0, :n] = comp
+    for rd in rounds:
+        tick, pos, prev = rd["state"]
+        assert len(rd["ask"]) == 100
+        for j in rng.choice(100, 3, replace=False):
+            _, w, _ = orc.race_sim(comp, L, 10_000, rd["mc_seed"], request=int(rd["requests"][j]),
+                                   state=rd["state"], stop_after=1, want_orders=False,
+                                   threads=8)
+            np.testing.assert_array_equal(rd["mc_probs"][j, :n], orc.win_probs(w))
+        fb = rd["fallback"]
+        assert fb.shape == (10_000, n)
+        for i in rng.choice(10_000, 3, replace=False):
+            _, w, _ = orc.race_sim(comp, L, 10_000, rd["fallback_seed"],
+                                   request=int(rd["fallback_base"] + i), state=rd["state"],
+                                   stop_after=1, want_orders=False, threads=8)
+            np.testing.assert_array_equal(fb[i], orc.win_probs(w))
+        X, slot = ref.encode(comp_b, [n], pos[None, :], prev[None, :], L, inputs.CFG_QUERY["dt"])
+        want_x = (ref.bf16(X).astype(np.float32).view(np.uint32) >> 16).astype(np.uint16)
+        assert (rd["x"].view(np.uint16) == want_x[0][None, :]).all()
+        _, qref, _ = ref.forward(params.astype(np.float64), ref.bf16(X), [n])
+        np.testing.assert_allclose(rd["sur_probs"][0], qref[0], atol=2e-3)
