@@ -330,3 +330,35 @@ def test_query_loop_full_size_sampled(torch, orc):
         assert (rd["x"].view(np.uint16) == want_x[0][None, :]).all()
         _, qref, _ = ref.forward(params.astype(np.float64), ref.bf16(X), [n])
         np.testing.assert_allclose(rd["sur_probs"][0], qref[0], atol=2e-3)
+
+
+def test_rp_bettor_loop_full_size_sampled(torch, orc):
+    """The RP(d) bettor loop at the size bench.py times (10^4 bettors with d
+    log-uniform in 1..200, 10^5 cheap bettors), two rounds: sampled bettors'
+    win counts and views, and sampled cheap bettors' views, against the
+    oracle one by one; the RP view counts against the views."""
+    q = inputs.query_race()
+    comp, seed, real = q["comp"], q["seed"], q["real_request"]
+    n = comp.shape[0]
+    rounds = []
+    announce("RP(d) bettor loop full size, 2 rounds")
+    res = bettors.run(n_bettors=10_000, d_lo=1, d_hi=200, every=1, max_rounds=2,
+                      n_cheap=100_000, report_every=0, log=lambda m: None,
+                      on_round=rounds.append)
+    assert res["rounds"] == 2
+    trace = orc.race_trace(comp, L, seed, real, 0, 10)
+    kinds, params = inputs.cheap_bettors(n_bettors=100_000)
+    rng = np.random.default_rng(8)
+    for rd in rounds:
+        d = rd["d"]
+        for i in rng.choice(10_000, 4, replace=False):
+            _, w, _ = orc.race_sim(comp, L, int(d[i]), rd["plan_seed"], request=int(i),
+                                   state=rd["state"], stop_after=1, want_orders=False, threads=8)
+            np.testing.assert_array_equal(rd["wins"][i, :n].astype(np.uint64), w)
+            v, _ = OB.rp_views(w[None, :], n)
+            assert rd["rp_views"][i] == v[0]
+        np.testing.assert_array_equal(np.bincount(rd["rp_views"], minlength=n), rd["rp_counts"])
+        for b in rng.choice(100_000, 20, replace=False):
+            want = OB.view(int(kinds[b]), float(params[b]), trace, rd["row"], L, 0, int(b),
+                           inputs.CFG_VIEWS["views_seed"])
+            assert rd["cheap_views"][b] == want, b
