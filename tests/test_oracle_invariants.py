@@ -2,7 +2,6 @@
 CPU oracle: complete tallies, label symmetry, resume from an in-play state,
 chunking of the simulation range, winner-only runs, RP(0) estimates."""
 import numpy as np
-import pytest
 from scipy import stats
 
 from paper_2108_02419_amd import inputs

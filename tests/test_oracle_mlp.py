@@ -2,7 +2,6 @@
 differences of the loss, closed forms of softmax cross-entropy and of the
 first Adam step, and properties of the state encoding."""
 import numpy as np
-import pytest
 
 from oracle import mlp
 
